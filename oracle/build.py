@@ -1,0 +1,27 @@
+"""Build the oracle's shared library with the host C compiler.
+
+Test infrastructure: compiles ``cggi_oracle.c`` (plain C, no GPU code) into
+``libcggi_oracle.so`` next to it.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cggi_oracle.c")
+LIB = os.path.join(HERE, "libcggi_oracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cc = os.environ.get("CC", "gcc")
+    tmp = LIB + ".tmp"
+    cmd = [cc, "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+           "-fno-strict-aliasing", "-o", tmp, SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
