@@ -1,0 +1,157 @@
+/*
+ * cggi.h -- C ABI of the MI355X (gfx950) batched CGGI gate-bootstrapping
+ * library libcggi.so.
+ *
+ * The method: ArctyrEX (arXiv 2306.11006), Section 2.2 "The CGGI
+ * Cryptosystem" and Fig. 1 "Encrypted Logic Gate Evaluation" -- a
+ * bootstrapped gate is a linear pre-op on LWE ciphertexts, a modulus switch
+ * of the result to Z_2N, an accumulator initialised to X^(-b~) * v, n CMux
+ * steps (rotate, subtract, gadget-decompose, multiply by a TRGSW row of the
+ * bootstrapping key, add), sample extraction, and a key switch back to the
+ * LWE key.  Section 4.2 ("waves") levelises a gate DAG so that every gate of
+ * a level is independent; Section 5.4 runs one batched launch per set of
+ * gates.
+ *
+ * Torus values are uint32_t (Z/2^32; the value u stands for u / 2^32) and
+ * every addition wraps mod 2^32.  All array arguments are DEVICE pointers
+ * (for example torch tensor data pointers) unless stated otherwise, are
+ * row-major and contiguous, and stay owned by the caller.  Layouts:
+ *   LWE ciphertext of dimension d : uint32_t[d + 1] = (a_0..a_{d-1}, b)
+ *   bootstrapping key (bsk)       : uint32_t[n][2l][2][N]; row r = c*l+(p-1)
+ *       (c = 0 mask / 1 body component being decomposed, p = 1..l gadget
+ *       level), then output component (0 = mask, 1 = body), then coefficient
+ *   key-switching key (ksk)       : uint32_t[N][t][2^gamma][n + 1]; entry
+ *       [j][p][h] is an LWE encryption of h * K_j * 2^(32 - (p+1)*gamma)
+ *
+ * Every entry point returns CGGI_OK (0) or a negative error code and, on
+ * error, leaves a message for cggi_last_error().  Shape and parameter errors
+ * are found on the host before anything is launched and leave every output
+ * untouched.  Batch calls are asynchronous on the given stream, allocate
+ * nothing while the workspace suffices (see cggi_ctx_reserve), never read
+ * device data on the host, and may be captured into a HIP graph.
+ * Calls on one context must not run concurrently from several host threads.
+ */
+#ifndef CGGI_H
+#define CGGI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Scheme parameters.  k must be 1 (one TRLWE mask polynomial).
+ * N in {256, 512, 1024, 2048}; gadget base Bg = 2^bg_bit with l levels;
+ * key switch base 2^ks_base_bit with ks_t levels. */
+typedef struct {
+    int32_t n, N, k, bg_bit, l, ks_base_bit, ks_t;
+} cggi_params_t;
+
+/* Forms of the negacyclic products inside the blind rotation.  Both give
+ * bit-identical results.
+ *  NTT : exact NTT modulo Q = 2^64 - 2^32 + 1 with the paper's generator
+ *        (Section 5.5), centred lift, low 32 bits.
+ *  INT8: exact split-limb block-Toeplitz GEMM on int8 MFMA with int32
+ *        accumulation; each key coefficient is split into four signed
+ *        8-bit limbs and the limbs are recombined mod 2^32. */
+typedef enum { CGGI_FORM_NTT = 1, CGGI_FORM_INT8 = 2 } cggi_form_t;
+
+enum {
+    CGGI_OK = 0,
+    CGGI_E_PARAM = -1,       /* unsupported or inconsistent parameters     */
+    CGGI_E_SHAPE = -2,       /* bad size, null or misaligned pointer        */
+    CGGI_E_ALIAS = -3,       /* output overlaps an input                    */
+    CGGI_E_HIP = -4,         /* a HIP runtime call failed                   */
+    CGGI_E_NOMEM = -5,       /* device allocation failed                    */
+    CGGI_E_UNSUPPORTED = -6  /* form not built into the context, or an
+                                allocation would be needed during capture   */
+};
+
+/* Gate opcodes of cggi_eval_level.  MUX(in0 = select, in1 = value if 1,
+ * in2 = value if 0) takes two bootstraps and one key switch; NOT, COPY and
+ * the constants take none; every other opcode takes one of each. */
+enum {
+    CGGI_NAND = 0, CGGI_AND = 1, CGGI_OR = 2, CGGI_XOR = 3, CGGI_MUX = 4,
+    CGGI_NOT = 5, CGGI_COPY = 6, CGGI_CONST0 = 7, CGGI_CONST1 = 8,
+    CGGI_NOR = 9, CGGI_XNOR = 10
+};
+
+typedef struct {
+    int32_t op, in0, in1, in2, out; /* wire indices; unused inputs ignored */
+} cggi_gate_t;
+
+typedef struct cggi_ctx cggi_ctx; /* opaque */
+
+/* Check a parameter set without touching the GPU.  Returns CGGI_OK or
+ * CGGI_E_PARAM (with a message).  Pure host code. */
+int cggi_params_check(const cggi_params_t *params);
+
+/* Create a context on the current HIP device.  Reads d_bsk
+ * ([n][2l][2][N]) once to derive the key forms selected by `forms` (a
+ * bitmask of cggi_form_t): the NTT form stores the bootstrapping key
+ * transformed mod Q (8 * n*2l*2*N bytes), the INT8 form stores its limb
+ * windows and a per-step offset correction.  d_bsk may be freed once this
+ * call returns (it synchronises `stream`).  d_ksk ([N][t][2^gamma][n+1])
+ * is NOT copied: it must stay valid and unchanged for the context's life.
+ * `stream` is a hipStream_t (NULL = default stream).  On success *out
+ * receives the context. */
+int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
+                    const uint32_t *d_ksk, uint32_t forms, void *stream,
+                    cggi_ctx **out);
+
+/* Free a context and everything it allocated (waits for the device).
+ * NULL is accepted. */
+int cggi_ctx_destroy(cggi_ctx *ctx);
+
+/* Pre-allocate the workspace of cggi_eval_level for levels of up to
+ * max_gates gates, so that later calls allocate nothing (required before
+ * graph capture).  cggi_bootstrap_batch and cggi_keyswitch_batch need no
+ * workspace. */
+int cggi_ctx_reserve(cggi_ctx *ctx, int32_t max_gates);
+
+/* Bootstrap a batch (Fig. 1, the looped steps plus sample extraction):
+ * for each of the B LWE ciphertexts d_in[B][n+1] (key s), modulus switch,
+ * initialise ACC = (0, X^(-b~) * v), run n CMux steps with the
+ * bootstrapping key, and extract coefficient 0 into d_out[B][N+1], an LWE
+ * ciphertext of dimension N under the TRLWE key.  d_testv is the test
+ * polynomial v ([N] torus values) or NULL for v = 2^29 * sum_j X^j (gate
+ * bootstrapping).  B == 0 is a no-op.  d_out must not overlap d_in or
+ * d_testv.  Bit-identical for both forms. */
+int cggi_bootstrap_batch(cggi_ctx *ctx, cggi_form_t form,
+                         const uint32_t *d_in, const uint32_t *d_testv,
+                         uint32_t *d_out, int32_t B, void *stream);
+
+/* Key switch a batch (Fig. 1, last step): d_in[B][N+1] (key K) ->
+ * d_out[B][n+1] (key s), out = (0,..,0, b') - sum_{j<N, p<t}
+ * ksk[j][p][digit_p(a'_j)], with unsigned base-2^gamma digits of a'_j
+ * rounded to t*gamma bits.  B == 0 is a no-op.  d_out must not overlap
+ * d_in. */
+int cggi_keyswitch_batch(cggi_ctx *ctx, const uint32_t *d_in,
+                         uint32_t *d_out, int32_t B, void *stream);
+
+/* Evaluate one level (Section 4.2 "wave") of a gate DAG in place on the
+ * wire array d_wires[W][n+1]: every gate reads its input wires and writes
+ * its output wire.  d_gates[G] is a device array of cggi_gate_t.  Contract
+ * (the levelizer guarantees it): no gate's out equals any input of a gate
+ * of the same level, and no two gates share an out.  A gate with an
+ * unknown opcode or a wire index outside [0, W) is skipped on the device
+ * (its output wire is not written); nothing is ever accessed out of
+ * bounds.  Gate pre-ops (Fig. 1 first
+ * box; bit 1 = +1/8, bit 0 = -1/8):
+ *   NAND (0,1/8)-x-y  AND (0,-1/8)+x+y  OR (0,1/8)+x+y  XOR (0,1/4)+2(x+y)
+ *   NOR (0,-1/8)-x-y  XNOR (0,-1/4)-2(x+y)  NOT -x  COPY x  CONST (0,+-1/8)
+ *   MUX u1 = BS((0,-1/8)+c+x), u2 = BS((0,-1/8)-c+y), out = KS((0,1/8)+u1+u2)
+ * G == 0 is a no-op.  Needs cggi_ctx_reserve(ctx, >= G) when called
+ * under graph capture. */
+int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
+                    const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
+                    int32_t W, void *stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *cggi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CGGI_H */

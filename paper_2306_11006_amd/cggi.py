@@ -1,0 +1,195 @@
+"""ctypes binding of libcggi.so (the C ABI declared in include/cggi.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library.  Device buffers are torch tensors (int32 or uint32
+dtype, contiguous, on the context's GPU); streams default to torch's current
+stream.  If the library has not been built, importing this module raises.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcggi.so")
+
+FORM_NTT = 1
+FORM_INT8 = 2
+FORMS = {"ntt": FORM_NTT, "int8": FORM_INT8}
+
+OK = 0
+E_PARAM, E_SHAPE, E_ALIAS, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, -4, \
+    -5, -6
+
+OPCODES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "MUX": 4, "NOT": 5,
+           "COPY": 6, "CONST0": 7, "CONST1": 8, "NOR": 9, "XNOR": 10}
+
+EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
+           "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
+           "cggi_eval_level", "cggi_last_error"]
+
+
+class CggiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cggi error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int32) for k in
+                ("n", "N", "k", "bg_bit", "l", "ks_base_bit", "ks_t")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcggi.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing; build it with "
+                "paper_2306_11006_amd/build.py (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        L.cggi_params_check.argtypes = [ctypes.POINTER(Params)]
+        L.cggi_ctx_create.argtypes = [ctypes.POINTER(Params), vp, vp,
+                                      ctypes.c_uint32, vp,
+                                      ctypes.POINTER(vp)]
+        L.cggi_ctx_destroy.argtypes = [vp]
+        L.cggi_ctx_reserve.argtypes = [vp, i32]
+        L.cggi_bootstrap_batch.argtypes = [vp, ctypes.c_int, vp, vp, vp, i32,
+                                           vp]
+        L.cggi_keyswitch_batch.argtypes = [vp, vp, vp, i32, vp]
+        L.cggi_eval_level.argtypes = [vp, ctypes.c_int, vp, i32, vp, i32, vp]
+        L.cggi_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS[:-1]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise CggiError(rc, lib().cggi_last_error().decode())
+
+
+def params_struct(p):
+    """Params from a paper_2306_11006_amd.params.Params or a tuple."""
+    vals = p.as_tuple() if hasattr(p, "as_tuple") else tuple(p)
+    return Params(*vals)
+
+
+def params_check(p):
+    """Return (code, message) of cggi_params_check (host only)."""
+    L = lib()
+    ps = params_struct(p)
+    rc = L.cggi_params_check(ctypes.byref(ps))
+    return rc, (L.cggi_last_error().decode() if rc else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("expected an int32/uint32 tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _form(form):
+    return FORMS[form] if isinstance(form, str) else int(form)
+
+
+class Context:
+    """A cggi_ctx: derived key forms for one parameter set on one GPU."""
+
+    def __init__(self, params, bsk, ksk, forms=("ntt", "int8"), stream=None):
+        self.params = params
+        self._ksk = ksk          # the library keeps a pointer to it
+        mask = 0
+        for f in forms:
+            mask |= _form(f)
+        self._ps = params_struct(params)
+        h = ctypes.c_void_p()
+        _check(lib().cggi_ctx_create(ctypes.byref(self._ps), _ptr(bsk),
+                                     _ptr(ksk), mask, _stream(stream),
+                                     ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().cggi_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reserve(self, max_gates):
+        _check(lib().cggi_ctx_reserve(self._h, int(max_gates)))
+
+    def bootstrap(self, form, inp, out=None, testv=None, stream=None):
+        p = self.params
+        B = inp.shape[0]
+        if out is None:
+            out = torch.empty((B, p.N + 1), dtype=torch.int32,
+                              device=inp.device)
+        _check(lib().cggi_bootstrap_batch(self._h, _form(form), _ptr(inp),
+                                          _ptr(testv), _ptr(out), B,
+                                          _stream(stream)))
+        return out
+
+    def keyswitch(self, inp, out=None, stream=None):
+        p = self.params
+        B = inp.shape[0]
+        if out is None:
+            out = torch.empty((B, p.n + 1), dtype=torch.int32,
+                              device=inp.device)
+        _check(lib().cggi_keyswitch_batch(self._h, _ptr(inp), _ptr(out), B,
+                                          _stream(stream)))
+        return out
+
+    def eval_level(self, form, gates, wires, stream=None):
+        """gates: int32 tensor [G, 5] (op, in0, in1, in2, out); wires:
+        int32 tensor [W, n+1], updated in place."""
+        G = gates.shape[0]
+        W = wires.shape[0]
+        _check(lib().cggi_eval_level(self._h, _form(form), _ptr(gates), G,
+                                     _ptr(wires), W, _stream(stream)))
+        return wires
+
+
+def to_device(a, device="cuda"):
+    """numpy uint32 array -> int32 CUDA tensor with the same bits."""
+    import numpy as np
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def to_host(t):
+    """int32 tensor -> numpy uint32 array with the same bits."""
+    import numpy as np
+    return t.cpu().numpy().view(np.uint32)

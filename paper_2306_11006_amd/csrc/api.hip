@@ -1,0 +1,326 @@
+// api.hip -- the C ABI of libcggi: validation, contexts, dispatch.
+//
+// Every shape and parameter error is detected here, on the host, before
+// anything is launched.
+#include "internal.hpp"
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+namespace cggi {
+
+size_t ntt_smem_bytes(int N, int n, int l);
+size_t int8_smem_bytes(int N, int R, int n);
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_error(hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    g_last_error = m;
+    return e == hipErrorOutOfMemory ? CGGI_E_NOMEM : CGGI_E_HIP;
+}
+
+constexpr size_t LDS_BYTES = 160 * 1024;
+
+int shape_of(const cggi_params_t *p, Shape *sh)
+{
+    if (!p)
+        return set_error(CGGI_E_PARAM, "params is NULL");
+    if (p->k != 1)
+        return set_error(CGGI_E_PARAM, "k must be 1");
+    if (p->N != 256 && p->N != 512 && p->N != 1024 && p->N != 2048)
+        return set_error(CGGI_E_PARAM, "N must be 256, 512, 1024 or 2048");
+    if (p->n < 1 || p->n > 1023)
+        return set_error(CGGI_E_PARAM, "n must be in [1, 1023]");
+    if (p->bg_bit < 1 || p->l < 1 || p->bg_bit * p->l > 31)
+        return set_error(CGGI_E_PARAM,
+                         "need bg_bit >= 1, l >= 1 and bg_bit * l <= 31");
+    if (p->ks_base_bit < 1 || p->ks_base_bit > 8 || p->ks_t < 1 ||
+        p->ks_base_bit * p->ks_t > 31)
+        return set_error(CGGI_E_PARAM, "need 1 <= ks_base_bit <= 8, "
+                                        "ks_t >= 1 and ks_base_bit * ks_t <= 31");
+    // Exactness of the NTT form: |sum of 2l*N products| < Q/2.
+    long double bound = (long double)(2 * p->l) * p->N *
+                        (long double)(1ull << (p->bg_bit - 1)) * 4294967295.0L;
+    if (bound >= 9.2e18L)
+        return set_error(CGGI_E_PARAM,
+                         "2l * N * 2^(bg_bit-1) * 2^32 must stay below Q/2");
+    Shape s{};
+    s.n = p->n;
+    s.N = p->N;
+    s.beta = p->bg_bit;
+    s.l = p->l;
+    s.gamma = p->ks_base_bit;
+    s.t = p->ks_t;
+    s.log2N = __builtin_ctz((unsigned)p->N);
+    s.S = p->bg_bit <= 7 ? 1 : (p->bg_bit <= 13 ? 2 : 0);
+    s.R = 2 * p->l * s.S;
+    s.nblk = p->N / 32;
+    s.elen = p->N + 64;
+    if (sh)
+        *sh = s;
+    return CGGI_OK;
+}
+
+static int check_form(const Shape &s, uint32_t form)
+{
+    if (form & CGGI_FORM_NTT) {
+        if (ntt_smem_bytes(s.N, s.n, s.l) > LDS_BYTES)
+            return set_error(CGGI_E_PARAM,
+                             "NTT form: (2l+3)*N*8 + 2(n+1) bytes exceed LDS");
+    }
+    if (form & CGGI_FORM_INT8) {
+        if (s.N > 1024)
+            return set_error(CGGI_E_PARAM, "INT8 form: N > 1024 not built");
+        if (s.S == 0)
+            return set_error(CGGI_E_PARAM, "INT8 form: bg_bit must be <= 13");
+        if (int8_smem_bytes(s.N, s.R, s.n) > LDS_BYTES)
+            return set_error(CGGI_E_PARAM, "INT8 form: workgroup exceeds LDS");
+    }
+    return CGGI_OK;
+}
+
+static bool aligned4(const void *p)
+{
+    return ((uintptr_t)p & 3u) == 0;
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + nb && b0 < a0 + na;
+}
+
+static int check_device(const Ctx *c)
+{
+    int dev = -1;
+    CGGI_HIP_TRY(hipGetDevice(&dev));
+    if (dev != c->device)
+        return set_error(CGGI_E_PARAM,
+                         "current device differs from the context's device");
+    return CGGI_OK;
+}
+
+static void free_ctx(Ctx *c)
+{
+    if (!c)
+        return;
+    (void)hipFree(c->bsk_ntt);
+    (void)hipFree(c->tw_fwd);
+    (void)hipFree(c->tw_inv);
+    (void)hipFree(c->bsk_i8);
+    (void)hipFree(c->corr);
+    (void)hipFree(c->ws_small);
+    (void)hipFree(c->ws_big);
+    (void)hipFree(c->ws_slot);
+    (void)hipFree(c->ws_count);
+    delete c;
+}
+
+static int reserve(Ctx *c, int32_t G, hipStream_t s)
+{
+    if (G <= c->ws_gates)
+        return CGGI_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CGGI_HIP_TRY(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return set_error(CGGI_E_UNSUPPORTED,
+                         "eval_level workspace too small under capture: call "
+                         "cggi_ctx_reserve first");
+    CGGI_HIP_TRY(hipDeviceSynchronize());
+    (void)hipFree(c->ws_small);
+    (void)hipFree(c->ws_big);
+    (void)hipFree(c->ws_slot);
+    (void)hipFree(c->ws_count);
+    c->ws_small = c->ws_big = nullptr;
+    c->ws_slot = c->ws_count = nullptr;
+    c->ws_gates = 0;
+    const size_t n1 = (size_t)c->sh.n + 1, N1 = (size_t)c->sh.N + 1;
+    if (hipMalloc(&c->ws_small, 2 * (size_t)G * n1 * 4) != hipSuccess ||
+        hipMalloc(&c->ws_big, 2 * (size_t)G * N1 * 4) != hipSuccess ||
+        hipMalloc(&c->ws_slot, (size_t)G * 4) != hipSuccess ||
+        hipMalloc(&c->ws_count, 16) != hipSuccess)
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the level workspace");
+    c->ws_gates = G;
+    return CGGI_OK;
+}
+
+} // namespace cggi
+
+using namespace cggi;
+
+extern "C" {
+
+int cggi_params_check(const cggi_params_t *params)
+{
+    return shape_of(params, nullptr);
+}
+
+int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
+                    const uint32_t *d_ksk, uint32_t forms, void *stream,
+                    cggi_ctx **out)
+{
+    if (!out)
+        return set_error(CGGI_E_SHAPE, "out is NULL");
+    *out = nullptr;
+    Shape sh;
+    int rc = shape_of(params, &sh);
+    if (rc)
+        return rc;
+    if (forms == 0 || (forms & ~(uint32_t)(CGGI_FORM_NTT | CGGI_FORM_INT8)))
+        return set_error(CGGI_E_PARAM, "forms must be a non-empty mask of "
+                                       "CGGI_FORM_NTT | CGGI_FORM_INT8");
+    if ((rc = check_form(sh, forms)))
+        return rc;
+    if (!d_bsk || !d_ksk || !aligned4(d_bsk) || !aligned4(d_ksk))
+        return set_error(CGGI_E_SHAPE, "bsk and ksk must be non-NULL and "
+                                       "4-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    cggi_ctx *c = new cggi_ctx();
+    c->p = *params;
+    c->sh = sh;
+    c->forms = forms;
+    c->ksk = d_ksk;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        free_ctx(c);
+        return set_error(CGGI_E_HIP, "hipGetDevice failed");
+    }
+    if (forms & CGGI_FORM_NTT) {
+        if ((rc = ntt_make_tables(c, s)) || (rc = ntt_transform_bsk(c, d_bsk, s))) {
+            free_ctx(c);
+            return rc;
+        }
+    }
+    if (forms & CGGI_FORM_INT8) {
+        if ((rc = int8_make_key(c, d_bsk, s))) {
+            free_ctx(c);
+            return rc;
+        }
+    }
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_ctx(c);
+        return hip_error(e, "hipStreamSynchronize after key derivation");
+    }
+    *out = c;
+    return CGGI_OK;
+}
+
+int cggi_ctx_destroy(cggi_ctx *ctx)
+{
+    if (!ctx)
+        return CGGI_OK;
+    (void)hipDeviceSynchronize();
+    free_ctx(ctx);
+    return CGGI_OK;
+}
+
+int cggi_ctx_reserve(cggi_ctx *ctx, int32_t max_gates)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (max_gates < 0 || max_gates > (1 << 22))
+        return set_error(CGGI_E_SHAPE, "max_gates must be in [0, 2^22]");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    return reserve(ctx, max_gates, nullptr);
+}
+
+int cggi_bootstrap_batch(cggi_ctx *ctx, cggi_form_t form,
+                         const uint32_t *d_in, const uint32_t *d_testv,
+                         uint32_t *d_out, int32_t B, void *stream)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (form != CGGI_FORM_NTT && form != CGGI_FORM_INT8)
+        return set_error(CGGI_E_PARAM, "unknown form");
+    if (!(ctx->forms & (uint32_t)form))
+        return set_error(CGGI_E_UNSUPPORTED, "form not built into the context");
+    if (B < 0 || B > (1 << 24))
+        return set_error(CGGI_E_SHAPE, "B must be in [0, 2^24]");
+    if (B == 0)
+        return CGGI_OK;
+    if (!d_in || !d_out || !aligned4(d_in) || !aligned4(d_out) ||
+        (d_testv && !aligned4(d_testv)))
+        return set_error(CGGI_E_SHAPE, "in/out must be non-NULL and 4-byte "
+                                       "aligned");
+    const size_t nin = (size_t)B * (ctx->sh.n + 1) * 4;
+    const size_t nout = (size_t)B * (ctx->sh.N + 1) * 4;
+    if (overlap(d_out, nout, d_in, nin) ||
+        (d_testv && overlap(d_out, nout, d_testv, (size_t)ctx->sh.N * 4)))
+        return set_error(CGGI_E_ALIAS, "out overlaps an input");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    return form == CGGI_FORM_INT8
+               ? int8_bootstrap(ctx, d_in, d_testv, d_out, B, nullptr, s)
+               : ntt_bootstrap(ctx, d_in, d_testv, d_out, B, nullptr, s);
+}
+
+int cggi_keyswitch_batch(cggi_ctx *ctx, const uint32_t *d_in,
+                         uint32_t *d_out, int32_t B, void *stream)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (B < 0 || B > (1 << 24))
+        return set_error(CGGI_E_SHAPE, "B must be in [0, 2^24]");
+    if (B == 0)
+        return CGGI_OK;
+    if (!d_in || !d_out || !aligned4(d_in) || !aligned4(d_out))
+        return set_error(CGGI_E_SHAPE, "in/out must be non-NULL and 4-byte "
+                                       "aligned");
+    const size_t nin = (size_t)B * (ctx->sh.N + 1) * 4;
+    const size_t nout = (size_t)B * (ctx->sh.n + 1) * 4;
+    if (overlap(d_out, nout, d_in, nin))
+        return set_error(CGGI_E_ALIAS, "out overlaps in");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    return keyswitch_launch(ctx, d_in, d_out, B, (hipStream_t)stream);
+}
+
+int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
+                    const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
+                    int32_t W, void *stream)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (form != CGGI_FORM_NTT && form != CGGI_FORM_INT8)
+        return set_error(CGGI_E_PARAM, "unknown form");
+    if (!(ctx->forms & (uint32_t)form))
+        return set_error(CGGI_E_UNSUPPORTED, "form not built into the context");
+    if (G < 0 || G > (1 << 22) || W < 1 || W > (1 << 26))
+        return set_error(CGGI_E_SHAPE, "need 0 <= G <= 2^22, 1 <= W <= 2^26");
+    if (G == 0)
+        return CGGI_OK;
+    if (!d_gates || !d_wires || !aligned4(d_gates) || !aligned4(d_wires))
+        return set_error(CGGI_E_SHAPE, "gates/wires must be non-NULL and "
+                                       "4-byte aligned");
+    if (overlap(d_gates, (size_t)G * sizeof(cggi_gate_t), d_wires,
+                (size_t)W * (ctx->sh.n + 1) * 4))
+        return set_error(CGGI_E_ALIAS, "gates overlap wires");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = reserve(ctx, G, s)))
+        return rc;
+    return level_launch(ctx, form, d_gates, G, d_wires, W, s);
+}
+
+const char *cggi_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+} // extern "C"

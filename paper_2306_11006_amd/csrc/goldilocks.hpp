@@ -1,0 +1,91 @@
+// goldilocks.hpp -- arithmetic modulo Q = 2^64 - 2^32 + 1 on gfx950.
+//
+// The modulus of the paper's exact NTT (Section 5.5): 2^64 = 2^32 - 1 and
+// 2^96 = -1 (mod Q), so a 128-bit product reduces with a few 64-bit adds.
+// All functions take and return canonical residues in [0, Q).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace cggi {
+namespace gl {
+
+constexpr uint64_t Q = 0xFFFFFFFF00000001ull;
+constexpr uint64_t EPS = 0xFFFFFFFFull; // 2^64 mod Q
+
+__host__ __device__ __forceinline__ uint64_t add(uint64_t a, uint64_t b)
+{
+    uint64_t r = a + b;
+    if (r < a)          // carry out of 2^64: add 2^64 mod Q
+        r += EPS;
+    if (r >= Q)
+        r -= Q;
+    return r;
+}
+
+__host__ __device__ __forceinline__ uint64_t sub(uint64_t a, uint64_t b)
+{
+    uint64_t r = a - b;
+    if (a < b)          // borrow of 2^64: subtract 2^64 mod Q
+        r -= EPS;
+    return r;
+}
+
+// (hi * 2^64 + lo) mod Q
+__host__ __device__ __forceinline__ uint64_t reduce128(uint64_t hi,
+                                                       uint64_t lo)
+{
+    uint64_t hh = hi >> 32;             // * 2^96 = -1
+    uint64_t hl = hi & 0xFFFFFFFFull;   // * 2^64 = 2^32 - 1
+    uint64_t t0 = lo - hh;
+    if (lo < hh)
+        t0 -= EPS;
+    uint64_t t1 = (hl << 32) - hl;
+    uint64_t r = t0 + t1;
+    if (r < t1)
+        r += EPS;
+    if (r >= Q)
+        r -= Q;
+    return r;
+}
+
+__device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b)
+{
+    return reduce128(__umul64hi(a, b), a * b);
+}
+
+inline uint64_t mul_host(uint64_t a, uint64_t b)
+{
+    unsigned __int128 p = (unsigned __int128)a * b;
+    return reduce128((uint64_t)(p >> 64), (uint64_t)p);
+}
+
+inline uint64_t pow_host(uint64_t b, uint64_t e)
+{
+    uint64_t r = 1;
+    while (e) {
+        if (e & 1)
+            r = mul_host(r, b);
+        b = mul_host(b, b);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Signed integer -> residue.
+__host__ __device__ __forceinline__ uint64_t from_i32(int32_t v)
+{
+    return v >= 0 ? (uint64_t)v : Q - (uint64_t)(-(int64_t)v);
+}
+
+// Residue of an integer Y with |Y| < Q/2 -> Y mod 2^32 (centred lift; the
+// low word of Q is 1, so a negative Y = y - Q has low word y_lo - 1).
+__host__ __device__ __forceinline__ uint32_t lift32(uint64_t y)
+{
+    uint32_t lo = (uint32_t)y;
+    return y > (Q >> 1) ? lo - 1u : lo;
+}
+
+} // namespace gl
+} // namespace cggi

@@ -1,0 +1,491 @@
+// int8_form.hip -- the int8-MFMA form of the blind rotation on gfx950.
+//
+// A CMux step (ArctyrEX Fig. 1 loop body) adds to each accumulator
+// component c' the sum over digit polynomials r of D_r * a_{r,c'} in
+// Z_{2^32}[X]/(X^N+1).  This file computes those products exactly as an
+// integer GEMM on v_mfma_i32_32x32x32_i8:
+//
+//  * Block-Toeplitz form.  With coefficients cut into blocks of 32
+//    (j = 32J + rho, m = 32M + kappa), (a * D)[j] =
+//    sum_Delta sum_kappa A_Delta[rho][kappa] * s(J,Delta) * D_{(J-Delta)
+//    mod N/32}[kappa], where A_Delta[rho][kappa] = a_ext[32 Delta + rho -
+//    kappa], a_ext[x] = a[x] for x >= 0 and -a[x+N] for x < 0, and
+//    s = -1 exactly when the block index wrapped (J < Delta).  For one
+//    Delta, A_Delta is a 32x32 matrix shared by every bootstrap, and the
+//    sign-rotated digit blocks of one bootstrap form a 32x32 (N = 1024)
+//    operand whose columns are the output blocks J.  So one bootstrap fills
+//    the MFMA column dimension by itself and the K loop runs over
+//    (r, Delta).
+//  * Limbs.  Each key value (negated in uint32 first where a_ext needs it,
+//    scaled by 2^(7s) for sub-digit s) is split into four signed int8
+//    limbs v = sum_q 2^(8q) v_q; the four limb GEMMs accumulate in int32
+//    and are recombined mod 2^32.
+//  * Digits.  Gadget digits in [-Bg/2, Bg/2) are split into 7-bit
+//    sub-digits delta in [-64, 64) (one for Bg <= 2^7).  The operand holds
+//    delta + 64 in [0, 128) so that the sign flip of wrapped blocks stays in
+//    int8; the extra 64 * sum_r a_r * (1 + X + .. + X^(N-1)) is a per-step
+//    constant precomputed at context creation and subtracted in the fold.
+//  * Exactness: |sum| <= R*N*128*127 < 2^31, so int32 never overflows, and
+//    the recombination is a ring identity mod 2^32.
+//
+// Launch layout: 256 threads (4 waves) per workgroup, one workgroup per CU
+// (LDS-limited).  A workgroup owns 4 column tiles = 4*1024/N bootstraps.
+// Wave w computes output component c' = w & 1 for column tiles 2(w>>1) and
+// 2(w>>1)+1 with four limb accumulators each (8 x 16 int32 registers).
+// LDS holds the accumulators, the digit operands (both signs), the step's
+// key windows in four byte-shifted copies (so every lane reads its 16-byte
+// Toeplitz row as four aligned dwords), double-buffered per digit
+// polynomial, and the modulus-switched inputs.
+#include "internal.hpp"
+
+namespace cggi {
+
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+constexpr int I8_THREADS = 256;
+constexpr int OFFSET = 64;      // digit operand bias
+
+template <int N> struct I8Cfg {
+    static constexpr int NB = N / 32;          // blocks per polynomial
+    static constexpr int GPT = 1024 / N;       // bootstraps per column tile
+    static constexpr int GPW = 4 * GPT;        // bootstraps per workgroup
+    static constexpr int ELEN = N + 64;        // bytes per limb window
+    static constexpr int EW = ELEN / 4;        // dwords per limb window
+    static constexpr int CW = N / 4 + 8;       // dwords of a shifted copy used
+    static constexpr int CLEN = N / 4 + 16;    // stride of a shifted copy
+    static constexpr int ECOP_DW = 2 * 2 * 4 * 4 * CLEN; // 2 buf, c', q, sigma
+};
+
+__device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
+{
+    return (u + (1u << (31 - log2_2n))) >> (32 - log2_2n);
+}
+
+// bsk [n][2l][2][N] -> limb windows [n][R][2][4][ELEN]
+//   window y of (i, r*S+s, c') holds a_ext[y - 31] * 2^(7s),
+//   a_ext[x] = a[x] (0 <= x < N), -a[x+N] (x < 0), 0 beyond N.
+template <int N>
+__global__ void k_int8_key(const uint32_t *__restrict__ bsk,
+                           int8_t *__restrict__ out, int n, int l, int S)
+{
+    using C = I8Cfg<N>;
+    const int R = 2 * l * S;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n * R * 2 * C::ELEN;
+    if (idx >= total)
+        return;
+    int y = (int)(idx % C::ELEN);
+    size_t t = idx / C::ELEN;
+    int cp = (int)(t % 2);
+    t /= 2;
+    int kb = (int)(t % R);
+    int i = (int)(t / R);
+    int r = kb / S, s = kb % S;
+    int x = y - 31;
+    const uint32_t *a = bsk + (((size_t)i * 2 * l + r) * 2 + cp) * N;
+    uint32_t v = 0;
+    if (x >= 0 && x < N)
+        v = a[x];
+    else if (x < 0)
+        v = 0u - a[x + N];
+    v <<= 7 * s;
+    int8_t *o = out + (((size_t)i * R + kb) * 2 + cp) * 4 * C::ELEN + y;
+    for (int q = 0; q < 4; ++q) {
+        int8_t limb = (int8_t)(v & 0xFFu);
+        o[(size_t)q * C::ELEN] = limb;
+        v = (v - (uint32_t)(int32_t)limb) >> 8;
+    }
+}
+
+// corr[i][c'][j] = 64 * (A * (1 + X + .. + X^(N-1)))[j] with
+// A = sum_r (sum_s 2^(7s)) a_{i,r,c'};  (A * 1)[j] = 2*prefix(j) - total.
+template <int N>
+__global__ __launch_bounds__(256) void k_int8_corr(
+    const uint32_t *__restrict__ bsk, uint32_t *__restrict__ corr, int l,
+    int S)
+{
+    __shared__ uint32_t A[N];
+    __shared__ uint32_t part[256];
+    const int i = blockIdx.x >> 1, cp = blockIdx.x & 1;
+    uint32_t w = 0;
+    for (int s = 0; s < S; ++s)
+        w += 1u << (7 * s);
+    for (int j = threadIdx.x; j < N; j += 256) {
+        uint32_t v = 0;
+        for (int r = 0; r < 2 * l; ++r)
+            v += bsk[(((size_t)i * 2 * l + r) * 2 + cp) * N + j];
+        A[j] = v * w;
+    }
+    __syncthreads();
+    // each thread scans a contiguous chunk, then the chunk totals
+    constexpr int CH = N / 256;
+    uint32_t run = 0;
+    for (int k = 0; k < CH; ++k) {
+        run += A[threadIdx.x * CH + k];
+        A[threadIdx.x * CH + k] = run;
+    }
+    part[threadIdx.x] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int k = 0; k < 256; ++k) {
+            uint32_t v = part[k];
+            part[k] = s;
+            s += v;
+        }
+    }
+    __syncthreads();
+    const uint32_t base = part[threadIdx.x];
+    for (int k = 0; k < CH; ++k)
+        A[threadIdx.x * CH + k] += base;
+    __syncthreads();
+    const uint32_t total = A[N - 1];
+    for (int j = threadIdx.x; j < N; j += 256)
+        corr[((size_t)i * 2 + cp) * N + j] =
+            (uint32_t)OFFSET * (2u * A[j] - total);
+}
+
+template <int N>
+struct I8Smem {
+    using C = I8Cfg<N>;
+    static constexpr size_t ecop = (size_t)C::ECOP_DW * 4;
+    static constexpr size_t acc = (size_t)C::GPW * 2 * N * 4;
+    static size_t dig(int R) { return (size_t)C::GPW * R * 2 * N; }
+    static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
+    static size_t total(int R, int n) { return ecop + acc + dig(R) + ms(n); }
+};
+
+template <int N>
+__global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
+    const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
+    const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
+    uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
+    int n, int beta, int l, int S)
+{
+    using C = I8Cfg<N>;
+    constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW;
+    constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW;
+    constexpr int LOG2_2N = __builtin_ctz(2 * N);
+    const int R = 2 * l * S;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);
+    uint32_t *acc = ecop + C::ECOP_DW;                       // [GPW][2][N]
+    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * 2 * N);
+    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPW * R * 2 * N);
+
+    int count = B;
+    if (d_count)
+        count = min(count, *d_count);
+    const int g0 = blockIdx.x * GPW;
+    if (g0 >= count)
+        return;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    // ---- modulus switch of the inputs --------------------------------
+    for (int idx = tid; idx < GPW * (n + 1); idx += I8_THREADS) {
+        int gl = idx / (n + 1), i = idx - gl * (n + 1);
+        int g = g0 + gl;
+        uint32_t u = g < count ? in[(size_t)g * (n + 1) + i] : 0u;
+        ms[idx] = (uint16_t)modswitch(u, LOG2_2N);
+    }
+    __syncthreads();
+    // ---- ACC = (0, X^(2N - b~) v) ---------------------------------------
+    for (int idx = tid; idx < GPW * N; idx += I8_THREADS) {
+        int gl = idx / N, m = idx - gl * N;
+        int e = (2 * N - ms[gl * (n + 1) + n]) & (2 * N - 1);
+        uint32_t v = testv ? testv[m] : (1u << 29);
+        int t = m + e;
+        if (t >= 2 * N) {
+            t -= 2 * N;
+        } else if (t >= N) {
+            t -= N;
+            v = 0u - v;
+        }
+        acc[(gl * 2 + 0) * N + t] = 0u;
+        acc[(gl * 2 + 1) * N + t] = v;
+    }
+
+    // ---- key-window staging ----------------------------------------------
+    // stage st = i*R + kb uses buffer st & 1; item = (array c'*4+q, word w)
+    constexpr int ITEMS = 8 * CW;
+    constexpr int PER_T = (ITEMS + I8_THREADS - 1) / I8_THREADS;
+    uint32_t pre_lo[PER_T], pre_hi[PER_T];
+    auto prefetch = [&](int st) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
+                              (size_t)st * 8 * EW;
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            int item = tid + k * I8_THREADS;
+            if (item < ITEMS) {
+                int arr = item / CW, w = item - arr * CW;
+                pre_lo[k] = src[arr * EW + w];
+                pre_hi[k] = src[arr * EW + w + 1];
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+        uint32_t *dst = ecop + buf * (2 * 4 * 4 * CLEN);
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            int item = tid + k * I8_THREADS;
+            if (item < ITEMS) {
+                int arr = item / CW, w = item - arr * CW;
+                uint32_t *d = dst + arr * 4 * CLEN + w;
+                d[0] = pre_lo[k];
+                d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
+                d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
+                d[3 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
+            }
+        }
+    };
+    prefetch(0);
+    stash(0);
+    __syncthreads();
+
+    // ---- per-lane constants ----------------------------------------------
+    const int cp = wave & 1;                 // output component of this wave
+    const int ct0 = 2 * (wave >> 1);         // first of its two column tiles
+    const int rho = lane & 31, hh = lane >> 5;
+    // A operand: dword offset of this lane inside one (buf, c', q) group
+    const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
+    // B operand: column c -> bootstrap (within tile) and output block J
+    const int colg = rho / NB, J = rho % NB;
+
+    const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
+    uint32_t dig_off = round_off;
+    for (int p = 1; p <= l; ++p)
+        dig_off += (1u << (beta - 1)) << (32 - p * beta);
+    const uint32_t bmask = (1u << beta) - 1u;
+    const int32_t bhalf = 1 << (beta - 1);
+
+    v16i Cacc[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                Cacc[t][q][v] = 0;
+
+    for (int i = 0; i < n; ++i) {
+        __syncthreads();   // ACC of the previous step complete
+        // ---- rotate, subtract, decompose into digit operands --------------
+        for (int item = tid; item < GPW * 2 * (N / 4); item += I8_THREADS) {
+            int gl = item / (2 * (N / 4));
+            int rem = item - gl * (2 * (N / 4));
+            int c = rem / (N / 4);
+            int m0 = 4 * (rem - c * (N / 4));
+            int e = ms[gl * (n + 1) + i];
+            const uint32_t *a = acc + (gl * 2 + c) * N;
+            uint32_t w4[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                int m = m0 + k;
+                int t = (m - e) & (2 * N - 1);
+                uint32_t rot = t < N ? a[t] : 0u - a[t - N];
+                w4[k] = rot - a[m] + dig_off;
+            }
+            // byte b of the dword holds coefficient m0 + 3 - b (reversed kappa)
+            int kap0 = m0 & 31, M = m0 >> 5;
+            int kp = 28 - kap0;                 // kappa' of byte 0
+            int off = (kp >> 4) * (NB * 16) + M * 16 + (kp & 15);
+            for (int p = 1; p <= l; ++p) {
+                int32_t d[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    d[k] = (int32_t)((w4[k] >> (32 - p * beta)) & bmask) - bhalf;
+                for (int s = 0; s < S; ++s) {
+                    uint32_t pos = 0, neg = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        int32_t sd;
+                        if (s == S - 1) {
+                            sd = d[k];
+                        } else {
+                            sd = ((d[k] + 64) & 127) - 64;
+                            d[k] = (d[k] - sd) >> 7;
+                        }
+                        uint32_t bp = (uint32_t)(sd + OFFSET) & 0xFFu;
+                        uint32_t bn = (uint32_t)(-(sd + OFFSET)) & 0xFFu;
+                        pos |= bp << (8 * (3 - k));
+                        neg |= bn << (8 * (3 - k));
+                    }
+                    int kb = ((c * l) + (p - 1)) * S + s;
+                    int8_t *base = dig + ((size_t)(gl * R + kb) * 2) * N;
+                    *reinterpret_cast<uint32_t *>(base + off) = pos;
+                    *reinterpret_cast<uint32_t *>(base + N + off) = neg;
+                }
+            }
+        }
+        __syncthreads();
+
+        // ---- K loop: digit polynomials x block offsets --------------------
+        for (int kb = 0; kb < R; ++kb) {
+            const int st = i * R + kb;
+            if (st + 1 < n * R)
+                prefetch(st + 1);
+            const uint32_t *eb = ecop + (st & 1) * (2 * 4 * 4 * CLEN) +
+                                 cp * (4 * 4 * CLEN) + a_lane;
+            const int8_t *db[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                int gl = (ct0 + t) * GPT + colg;
+                db[t] = dig + ((size_t)(gl * R + kb) * 2) * N + hh * (NB * 16);
+            }
+            for (int dl = 0; dl < NB; ++dl) {
+                const int Mb = (J - dl) & (NB - 1);
+                const int sg = J < dl ? N : 0;
+                v4i bfr[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    bfr[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t *ap = eb + q * (4 * CLEN) + 8 * dl;
+                    v4i afr;
+                    afr[0] = (int)ap[0];
+                    afr[1] = (int)ap[1];
+                    afr[2] = (int)ap[2];
+                    afr[3] = (int)ap[3];
+#pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            afr, bfr[t], Cacc[t][q], 0, 0, 0);
+                }
+            }
+            if (st + 1 < n * R)
+                stash((st + 1) & 1);
+            __syncthreads();
+        }
+
+        // ---- fold limbs, subtract the offset correction, add into ACC -----
+        const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            int gl = (ct0 + t) * GPT + colg;
+            uint32_t *a = acc + (gl * 2 + cp) * N + 32 * J;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                int row = 8 * (v >> 2) + 4 * hh + (v & 3);
+                uint32_t x = (uint32_t)Cacc[t][0][v] +
+                             ((uint32_t)Cacc[t][1][v] << 8) +
+                             ((uint32_t)Cacc[t][2][v] << 16) +
+                             ((uint32_t)Cacc[t][3][v] << 24);
+                a[row] += x - cr[32 * J + row];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    Cacc[t][q][v] = 0;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- sample extraction ---------------------------------------------------
+    for (int idx = tid; idx < GPW * (N + 1); idx += I8_THREADS) {
+        int gl = idx / (N + 1), j = idx - gl * (N + 1);
+        int g = g0 + gl;
+        if (g >= count)
+            continue;
+        const uint32_t *a = acc + gl * 2 * N;
+        uint32_t v;
+        if (j == 0)
+            v = a[0];
+        else if (j < N)
+            v = 0u - a[N - j];
+        else
+            v = a[N];
+        out[(size_t)g * (N + 1) + j] = v;
+    }
+}
+
+} // namespace
+
+size_t int8_smem_bytes(int N, int R, int n)
+{
+    switch (N) {
+    case 256: return I8Smem<256>::total(R, n);
+    case 512: return I8Smem<512>::total(R, n);
+    case 1024: return I8Smem<1024>::total(R, n);
+    default: return (size_t)-1;
+    }
+}
+
+template <int N>
+static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
+{
+    using C = I8Cfg<N>;
+    const Shape &sh = c->sh;
+    size_t kbytes = (size_t)sh.n * sh.R * 2 * 4 * C::ELEN;
+    size_t cbytes = (size_t)sh.n * 2 * N * sizeof(uint32_t);
+    if (hipMalloc(&c->bsk_i8, kbytes) != hipSuccess) {
+        c->bsk_i8 = nullptr;
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the int8 key failed");
+    }
+    if (hipMalloc(&c->corr, cbytes) != hipSuccess) {
+        c->corr = nullptr;
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the int8 correction failed");
+    }
+    size_t total = (size_t)sh.n * sh.R * 2 * C::ELEN;
+    int blocks = (int)((total + 255) / 256);
+    hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
+                       c->bsk_i8, sh.n, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_int8_corr<N>, dim3(sh.n * 2), dim3(256), 0, s, bsk,
+                       c->corr, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
+{
+    switch (c->sh.N) {
+    case 256: return make_key_n<256>(c, bsk, s);
+    case 512: return make_key_n<512>(c, bsk, s);
+    case 1024: return make_key_n<1024>(c, bsk, s);
+    default: return set_error(CGGI_E_PARAM, "INT8 form: N must be 256..1024");
+    }
+}
+
+template <int N>
+static int launch_bs_int8(const Ctx *c, const uint32_t *in,
+                          const uint32_t *testv, uint32_t *out, int B,
+                          const int32_t *d_count, hipStream_t s)
+{
+    using C = I8Cfg<N>;
+    const Shape &sh = c->sh;
+    size_t smem = I8Smem<N>::total(sh.R, sh.n);
+    static bool attr_done = false;
+    if (!attr_done) {
+        CGGI_HIP_TRY(hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&k_bootstrap_int8<N>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_done = true;
+    }
+    int grid = (B + C::GPW - 1) / C::GPW;
+    hipLaunchKernelGGL(k_bootstrap_int8<N>, dim3(grid), dim3(I8_THREADS),
+                       smem, s, c->bsk_i8, c->corr, in, testv, out, B,
+                       d_count, sh.n, sh.beta, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                   uint32_t *out, int B, const int32_t *d_count,
+                   hipStream_t s)
+{
+    switch (c->sh.N) {
+    case 256: return launch_bs_int8<256>(c, in, testv, out, B, d_count, s);
+    case 512: return launch_bs_int8<512>(c, in, testv, out, B, d_count, s);
+    case 1024: return launch_bs_int8<1024>(c, in, testv, out, B, d_count, s);
+    default: return set_error(CGGI_E_PARAM, "INT8 form: N must be 256..1024");
+    }
+}
+
+} // namespace cggi

@@ -1,0 +1,85 @@
+// internal.hpp -- shared host-side declarations of libcggi (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/cggi.h"
+
+namespace cggi {
+
+// Derived parameter values used by the launchers.
+struct Shape {
+    int n, N, beta, l, gamma, t;
+    int log2N;
+    int R;        // digit polynomials per CMux step in the INT8 form: 2l*S
+    int S;        // 7-bit sub-digits per gadget digit (INT8 form)
+    int nblk;     // N / 32 blocks of the block-Toeplitz product
+    int elen;     // bytes per limb window of the INT8 key form
+};
+
+} // namespace cggi
+
+// The context behind the opaque handle of cggi.h.
+struct cggi_ctx {
+    cggi_params_t p;
+    cggi::Shape sh;
+    int device;
+    uint32_t forms;
+    const uint32_t *ksk;          // caller-owned [N][t][2^gamma][n+1]
+    // NTT form
+    uint64_t *bsk_ntt = nullptr;  // [n][2l][2][N] mod Q, bit-reversed order
+    uint64_t *tw_fwd = nullptr;   // [N] psi^bitrev(i)
+    uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
+    // INT8 form
+    int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
+    uint32_t *corr = nullptr;     // [n][2][N] offset correction per step
+    // eval_level workspace
+    int32_t ws_gates = 0;
+    uint32_t *ws_small = nullptr; // [2G][n+1] bootstrap inputs
+    uint32_t *ws_big = nullptr;   // [2G][N+1] bootstrap outputs
+    int32_t *ws_slot = nullptr;   // [G] first slot of each gate (-1: none)
+    int32_t *ws_count = nullptr;  // [1] number of bootstrap slots
+};
+
+namespace cggi {
+
+using Ctx = ::cggi_ctx;
+
+// Error plumbing (thread-local message).
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+
+#define CGGI_HIP_TRY(expr)                                                   \
+    do {                                                                     \
+        hipError_t e_ = (expr);                                              \
+        if (e_ != hipSuccess)                                                \
+            return ::cggi::hip_error(e_, #expr);                             \
+    } while (0)
+
+int shape_of(const cggi_params_t *p, Shape *sh);
+
+// Kernel launchers (each returns CGGI_OK or an error code).
+int ntt_make_tables(Ctx *c, hipStream_t s);
+int ntt_transform_bsk(Ctx *c, const uint32_t *bsk, hipStream_t s);
+int ntt_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                  uint32_t *out, int B, const int32_t *d_count,
+                  hipStream_t s);
+
+int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s);
+int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                   uint32_t *out, int B, const int32_t *d_count,
+                   hipStream_t s);
+
+// Key switch.  in_a/in_b: optional second input added before switching
+// (MUX combine); the plain batch call passes null maps.
+int keyswitch_launch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
+                     hipStream_t s);
+
+int level_launch(Ctx *c, cggi_form_t form, const cggi_gate_t *gates, int G,
+                 uint32_t *wires, int W, hipStream_t s);
+
+} // namespace cggi

@@ -1,0 +1,310 @@
+// ntt_form.hip -- the NTT form of the blind rotation on gfx950.
+//
+// Every negacyclic product of a CMux step (ArctyrEX Fig. 1: forward
+// transforms of the decomposed digit polynomials, pointwise product with
+// the transformed TRGSW row, inverse transforms, add into the accumulator)
+// is computed exactly modulo Q = 2^64 - 2^32 + 1 with psi = g^(2^32 / 2N)
+// for the paper's generator g (Section 5.5).  Since every exact sum is
+// below Q/2 in magnitude (checked on the host), the centred lift of the
+// result equals the integer product, and its low 32 bits are the product
+// mod 2^32.
+//
+// Layout: one workgroup of 256 threads owns one bootstrap.  LDS holds the
+// accumulator (2 x N u32), the 2l digit transforms (2l x N u64) and the two
+// product transforms (2 x N u64).  The transformed key row of step i
+// ([2l][2][N] u64) streams from L2 / Infinity Cache; it is shared by every
+// workgroup.
+#include "goldilocks.hpp"
+#include "internal.hpp"
+
+#include <vector>
+
+namespace cggi {
+
+namespace {
+
+constexpr int NTT_THREADS = 256;
+constexpr uint64_t G_PAPER = 12037493425763644479ull; // order 2^32 mod Q
+
+unsigned bitrev(unsigned x, int bits)
+{
+    unsigned r = 0;
+    for (int i = 0; i < bits; ++i)
+        r |= ((x >> i) & 1u) << (bits - 1 - i);
+    return r;
+}
+
+// In-place negacyclic forward NTT of P polynomials of length N in LDS
+// (Cooley-Tukey, psi-twisted, output in bit-reversed order).
+template <int N>
+__device__ __forceinline__ void ntt_fwd(uint64_t *a, int P,
+                                        const uint64_t *__restrict__ tw)
+{
+    constexpr int H = N / 2;
+    int t = N;
+    for (int m = 1; m < N; m <<= 1) {
+        t >>= 1;
+        for (int idx = threadIdx.x; idx < P * H; idx += NTT_THREADS) {
+            int poly = idx / H, k = idx - poly * H;
+            int i = k / t, j = k - i * t;
+            uint64_t *x = a + poly * N + 2 * i * t + j;
+            uint64_t S = tw[m + i];
+            uint64_t U = x[0], V = gl::mul(x[t], S);
+            x[0] = gl::add(U, V);
+            x[t] = gl::sub(U, V);
+        }
+        __syncthreads();
+    }
+}
+
+// In-place inverse (Gentleman-Sande, bit-reversed input, natural output),
+// without the final 1/N scaling.
+template <int N>
+__device__ __forceinline__ void ntt_inv(uint64_t *a, int P,
+                                        const uint64_t *__restrict__ twi)
+{
+    constexpr int H = N / 2;
+    int t = 1;
+    for (int m = N; m > 1; m >>= 1) {
+        int h = m >> 1;
+        for (int idx = threadIdx.x; idx < P * H; idx += NTT_THREADS) {
+            int poly = idx / H, k = idx - poly * H;
+            int i = k / t, j = k - i * t;
+            uint64_t *x = a + poly * N + 2 * i * t + j;
+            uint64_t S = twi[h + i];
+            uint64_t U = x[0], V = x[t];
+            x[0] = gl::add(U, V);
+            x[t] = gl::mul(gl::sub(U, V), S);
+        }
+        __syncthreads();
+        t <<= 1;
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(NTT_THREADS) void k_bsk_to_ntt(
+    const uint32_t *__restrict__ bsk, uint64_t *__restrict__ out,
+    const uint64_t *__restrict__ tw, int npoly)
+{
+    __shared__ uint64_t a[N];
+    int poly = blockIdx.x;
+    if (poly >= npoly)
+        return;
+    for (int j = threadIdx.x; j < N; j += NTT_THREADS)
+        a[j] = bsk[(size_t)poly * N + j];   // torus value as a residue
+    __syncthreads();
+    ntt_fwd<N>(a, 1, tw);
+    for (int j = threadIdx.x; j < N; j += NTT_THREADS)
+        out[(size_t)poly * N + j] = a[j];
+}
+
+__device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
+{
+    return (u + (1u << (31 - log2_2n))) >> (32 - log2_2n);
+}
+
+// One bootstrap per workgroup.
+template <int N>
+__global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
+    const uint64_t *__restrict__ bsk_ntt, const uint64_t *__restrict__ tw,
+    const uint64_t *__restrict__ twi, uint64_t ninv,
+    const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
+    uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
+    int n, int beta, int l)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L2 = 2 * l;
+    uint64_t *dig = reinterpret_cast<uint64_t *>(smem);          // [2l][N]
+    uint64_t *res = dig + (size_t)L2 * N;                         // [2][N]
+    uint32_t *acc = reinterpret_cast<uint32_t *>(res + 2 * N);    // [2][N]
+    uint16_t *ms = reinterpret_cast<uint16_t *>(acc + 2 * N);     // [n+1]
+
+    int count = B;
+    if (d_count)
+        count = min(count, *d_count);
+    const int g = blockIdx.x;
+    if (g >= count)
+        return;
+    constexpr int LOG2_2N = __builtin_ctz(2 * N);
+    const uint32_t *ct = in + (size_t)g * (n + 1);
+    for (int i = threadIdx.x; i <= n; i += NTT_THREADS)
+        ms[i] = (uint16_t)modswitch(ct[i], LOG2_2N);
+    __syncthreads();
+
+    // ACC = (0, X^(2N - b~) * v)
+    {
+        int e = (2 * N - ms[n]) & (2 * N - 1);
+        for (int m = threadIdx.x; m < N; m += NTT_THREADS) {
+            uint32_t v = testv ? testv[m] : (1u << 29);
+            int t = m + e;
+            if (t >= 2 * N) {
+                t -= 2 * N;
+            } else if (t >= N) {
+                t -= N;
+                v = 0u - v;
+            }
+            acc[t] = 0u;
+            acc[N + t] = v;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
+    uint32_t dig_off = round_off;
+    for (int p = 1; p <= l; ++p)
+        dig_off += (1u << (beta - 1)) << (32 - p * beta);
+    const uint32_t bmask = (1u << beta) - 1u;
+    const int32_t bhalf = 1 << (beta - 1);
+
+    for (int i = 0; i < n; ++i) {
+        const int e = ms[i];
+        if (e == 0)      // X^0 * ACC - ACC = 0 decomposes to all-zero digits
+            continue;
+        // rotate, subtract, decompose
+        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS) {
+            int c = idx / N, m = idx - c * N;
+            int t = (m - e) & (2 * N - 1);
+            uint32_t rot = t < N ? acc[c * N + t] : 0u - acc[c * N + t - N];
+            uint32_t w = rot - acc[c * N + m] + dig_off;
+            for (int p = 1; p <= l; ++p) {
+                int32_t d = (int32_t)((w >> (32 - p * beta)) & bmask) - bhalf;
+                dig[(size_t)(c * l + p - 1) * N + m] = gl::from_i32(d);
+            }
+        }
+        __syncthreads();
+        ntt_fwd<N>(dig, L2, tw);
+        // pointwise: res[c'][k] = sum_r dig[r][k] * bsk_ntt[i][r][c'][k]
+        const uint64_t *row = bsk_ntt + (size_t)i * L2 * 2 * N;
+        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS) {
+            int cp = idx / N, k = idx - cp * N;
+            uint64_t s = 0;
+            for (int r = 0; r < L2; ++r)
+                s = gl::add(s, gl::mul(dig[(size_t)r * N + k],
+                                       row[((size_t)r * 2 + cp) * N + k]));
+            res[cp * N + k] = s;
+        }
+        __syncthreads();
+        ntt_inv<N>(res, 2, twi);
+        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS)
+            acc[idx] += gl::lift32(gl::mul(res[idx], ninv));
+        __syncthreads();
+    }
+
+    // sample extraction of coefficient 0
+    uint32_t *o = out + (size_t)g * (N + 1);
+    for (int j = threadIdx.x; j <= N; j += NTT_THREADS) {
+        uint32_t v;
+        if (j == 0)
+            v = acc[0];
+        else if (j < N)
+            v = 0u - acc[N - j];
+        else
+            v = acc[N];
+        o[j] = v;
+    }
+}
+
+template <int N>
+size_t ntt_smem(int n, int l)
+{
+    return (size_t)2 * l * N * 8 + 2 * N * 8 + 2 * N * 4 +
+           (size_t)(n + 1) * 2 + 16;
+}
+
+} // namespace
+
+int ntt_make_tables(Ctx *c, hipStream_t s)
+{
+    const int N = c->sh.N, logN = c->sh.log2N;
+    uint64_t psi = gl::pow_host(G_PAPER, (1ull << 32) / (2ull * N));
+    uint64_t psi_inv = gl::pow_host(psi, 2ull * N - 1);
+    std::vector<uint64_t> f(N), iv(N);
+    for (int i = 0; i < N; ++i) {
+        unsigned r = bitrev((unsigned)i, logN);
+        f[i] = gl::pow_host(psi, r);
+        iv[i] = gl::pow_host(psi_inv, r);
+    }
+    CGGI_HIP_TRY(hipMalloc(&c->tw_fwd, N * sizeof(uint64_t)));
+    CGGI_HIP_TRY(hipMalloc(&c->tw_inv, N * sizeof(uint64_t)));
+    CGGI_HIP_TRY(hipMemcpyAsync(c->tw_fwd, f.data(), N * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, s));
+    CGGI_HIP_TRY(hipMemcpyAsync(c->tw_inv, iv.data(), N * sizeof(uint64_t),
+                                hipMemcpyHostToDevice, s));
+    CGGI_HIP_TRY(hipStreamSynchronize(s));
+    return CGGI_OK;
+}
+
+int ntt_transform_bsk(Ctx *c, const uint32_t *bsk, hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    int npoly = sh.n * 2 * sh.l * 2;
+    size_t bytes = (size_t)npoly * sh.N * sizeof(uint64_t);
+    if (hipMalloc(&c->bsk_ntt, bytes) != hipSuccess) {
+        c->bsk_ntt = nullptr;
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the NTT key failed");
+    }
+    switch (sh.N) {
+    case 256:
+        hipLaunchKernelGGL(k_bsk_to_ntt<256>, dim3(npoly), dim3(NTT_THREADS),
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+        break;
+    case 512:
+        hipLaunchKernelGGL(k_bsk_to_ntt<512>, dim3(npoly), dim3(NTT_THREADS),
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+        break;
+    case 1024:
+        hipLaunchKernelGGL(k_bsk_to_ntt<1024>, dim3(npoly), dim3(NTT_THREADS),
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+        break;
+    case 2048:
+        hipLaunchKernelGGL(k_bsk_to_ntt<2048>, dim3(npoly), dim3(NTT_THREADS),
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+        break;
+    default:
+        return set_error(CGGI_E_PARAM, "NTT form: unsupported N");
+    }
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+template <int N>
+static int launch_bs_ntt(const Ctx *c, const uint32_t *in,
+                         const uint32_t *testv, uint32_t *out, int B,
+                         const int32_t *d_count, hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    size_t smem = ntt_smem<N>(sh.n, sh.l);
+    static bool attr_done = false;
+    if (!attr_done) {
+        CGGI_HIP_TRY(hipFuncSetAttribute(
+            reinterpret_cast<const void *>(&k_bootstrap_ntt<N>),
+            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_done = true;
+    }
+    uint64_t ninv = gl::pow_host((uint64_t)N, gl::Q - 2);
+    hipLaunchKernelGGL(k_bootstrap_ntt<N>, dim3(B), dim3(NTT_THREADS), smem,
+                       s, c->bsk_ntt, c->tw_fwd, c->tw_inv, ninv, in, testv,
+                       out, B, d_count, sh.n, sh.beta, sh.l);
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+int ntt_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                  uint32_t *out, int B, const int32_t *d_count, hipStream_t s)
+{
+    switch (c->sh.N) {
+    case 256: return launch_bs_ntt<256>(c, in, testv, out, B, d_count, s);
+    case 512: return launch_bs_ntt<512>(c, in, testv, out, B, d_count, s);
+    case 1024: return launch_bs_ntt<1024>(c, in, testv, out, B, d_count, s);
+    case 2048: return launch_bs_ntt<2048>(c, in, testv, out, B, d_count, s);
+    default: return set_error(CGGI_E_PARAM, "NTT form: unsupported N");
+    }
+}
+
+size_t ntt_smem_bytes(int N, int n, int l)
+{
+    return (size_t)2 * l * N * 8 + 2 * N * 8 + 2 * N * 4 +
+           (size_t)(n + 1) * 2 + 16;
+}
+
+} // namespace cggi

@@ -1,0 +1,100 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/cggi.h declares, and rejects bad parameters on the host (no GPU
+call is made by any of these tests)."""
+import os
+import re
+
+import pytest
+
+from paper_2306_11006_amd import params
+from paper_2306_11006_amd import cggi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include",
+                      "cggi.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cggi_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "cggi_bootstrap_batch" in names and len(names) >= 8
+    L = cggi.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(cggi.EXPORTS) == names
+
+
+@pytest.mark.parametrize("p", [params.TOY, params.DEFAULT, params.LARGE])
+def test_params_accepted(p):
+    assert cggi.params_check(p) == (0, "")
+
+
+BAD = [
+    (dict(k=2), "k must be 1"),
+    (dict(N=300), "N must be"),
+    (dict(N=4096), "N must be"),
+    (dict(n=0), "n must be"),
+    (dict(n=2000), "n must be"),
+    (dict(bg_bit=0), "bg_bit"),
+    (dict(bg_bit=11, l=3), "bg_bit * l"),
+    (dict(ks_base_bit=0), "ks_base_bit"),
+    (dict(ks_base_bit=4, ks_t=8), "ks_base_bit * ks_t"),
+    (dict(bg_bit=30, l=1, N=2048), "Q/2"),
+]
+
+
+@pytest.mark.parametrize("change,msg", BAD)
+def test_params_rejected(change, msg):
+    import dataclasses
+    p = dataclasses.replace(params.DEFAULT, **change)
+    rc, text = cggi.params_check(p)
+    assert rc == cggi.E_PARAM
+    assert msg in text
+
+
+def test_null_params_rejected():
+    L = cggi.lib()
+    assert L.cggi_params_check(None) == cggi.E_PARAM
+    assert b"NULL" in L.cggi_last_error()
+
+
+def test_create_rejects_bad_arguments_before_any_gpu_work():
+    import ctypes
+    L = cggi.lib()
+    ps = cggi.params_struct(params.TOY)
+    h = ctypes.c_void_p()
+    # null output handle
+    assert L.cggi_ctx_create(ctypes.byref(ps), None, None, 1, None,
+                             None) == cggi.E_SHAPE
+    # empty / unknown form mask
+    assert L.cggi_ctx_create(ctypes.byref(ps), None, None, 0, None,
+                             ctypes.byref(h)) == cggi.E_PARAM
+    assert L.cggi_ctx_create(ctypes.byref(ps), None, None, 4, None,
+                             ctypes.byref(h)) == cggi.E_PARAM
+    # null keys
+    assert L.cggi_ctx_create(ctypes.byref(ps), None, None, 1, None,
+                             ctypes.byref(h)) == cggi.E_SHAPE
+    # misaligned keys
+    assert L.cggi_ctx_create(ctypes.byref(ps), ctypes.c_void_p(2),
+                             ctypes.c_void_p(8), 1, None,
+                             ctypes.byref(h)) == cggi.E_SHAPE
+    # int8 form needs N <= 1024
+    pl = cggi.params_struct(params.LARGE)
+    assert L.cggi_ctx_create(ctypes.byref(pl), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), 2, None,
+                             ctypes.byref(h)) == cggi.E_PARAM
+    assert h.value is None
+
+
+def test_batch_calls_reject_null_context():
+    L = cggi.lib()
+    assert L.cggi_bootstrap_batch(None, 1, None, None, None, 4,
+                                  None) == cggi.E_PARAM
+    assert L.cggi_keyswitch_batch(None, None, None, 4, None) == cggi.E_PARAM
+    assert L.cggi_eval_level(None, 1, None, 1, None, 1, None) == cggi.E_PARAM
+    assert L.cggi_ctx_reserve(None, 4) == cggi.E_PARAM
+    assert L.cggi_ctx_destroy(None) == cggi.OK
