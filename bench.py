@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Gate bootstraps per second on one MI355X.
+
+Workload: one level of 1024 independent NAND gates at n=630, N=1024,
+Bg=2^7 l=3, key switch base 2^2 t=8 (the default parameter set).  A step is
+one cggi_eval_level call over that level: linear pre-op, modulus switch,
+accumulator init, 630 CMux steps, sample extraction and key switch for every
+gate, writing the 1024 output wires.  Inputs and keys are resident in HBM
+before timing starts.  The int8-MFMA form gives `value`; the NTT form is
+timed on the same batch and reported beside it.
+
+Keys and ciphertexts are seeded uniform arrays: real ones are
+indistinguishable from uniform under the LWE assumption and every kernel's
+work is independent of the values.  The CPU baseline runs the plain C
+oracle on a bounded sample of the same gates (and checks those gates' GPU
+outputs bit for bit).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("gate bootstraps/sec on 1 MI355X (N=1024), int8-MFMA vs NTT form, "
+          "bit-exact")
+PEAK_INT8_TOPS = 5000.0      # dense int8 MFMA, MI355X
+# NTT form: one Goldilocks multiply-mod needs four 32x32->64-bit products;
+# 64-bit integer multiply-add issues at a quarter of the 64 lanes/clk of a
+# CU, so the products alone cap the rate at 256 CUs * 16 / 4 * 2.4 GHz.
+PEAK_MULMOD_T = 256 * 16 / 4 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def int8_ops_per_bootstrap(p):
+    S = 1 if p.bg_bit <= 7 else 2
+    return 2 * (2 * p.N) * (2 * p.l * p.N * S) * 4 * p.n
+
+
+def ntt_mulmods_per_bootstrap(p):
+    logN = p.N.bit_length() - 1
+    per_ntt = (p.N // 2) * logN
+    return p.n * ((2 * p.l + 2) * per_ntt + 2 * p.l * 2 * p.N)
+
+
+def cpu_baseline(p, bsk, ksk, wires_np, gates_np, out_gpu, sample, threads):
+    """Time the oracle on `sample` gates of the batch with `threads` host
+    threads; compare those gates' outputs with the GPU's."""
+    import numpy as np
+    import oracle as O
+    O.lib()
+
+    def one(g):
+        op, a, b, _, _ = gates_np[g]
+        return O.gate(p, int(op), bsk, ksk, wires_np[a], wires_np[b])
+
+    idx = list(range(sample))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        outs = list(ex.map(one, idx))
+    wall = time.perf_counter() - t0
+    # out_gpu holds the output wires in gate order
+    ok = all(np.array_equal(outs[i], out_gpu[g]) for i, g in enumerate(idx))
+    return sample / wall, wall, ok
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--gates", type=int, default=1024)
+    ap.add_argument("--forms", default="int8,ntt")
+    ap.add_argument("--cpu-sample", type=int, default=16,
+                    help="gates the oracle runs for the CPU baseline (0: skip)")
+    ap.add_argument("--seed", type=int, default=2306)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the batched bootstrap runs on "
+              "a single MI355X (multi-GPU sharding of a level is a design "
+              "note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2306_11006_amd import cggi, inputs, params
+
+    p = params.DEFAULT
+    G = args.gates
+    forms = [f for f in args.forms.split(",") if f]
+    log(f"[bench] params n={p.n} N={p.N} Bg=2^{p.bg_bit} l={p.l} "
+        f"KS 2^{p.ks_base_bit}x{p.ks_t}; {G} NAND gates; forms {forms}")
+    bsk, ksk = inputs.uniform_keys(p, args.seed)
+    wires_np = inputs.uniform_lwe(p, args.seed + 1, 3 * G)
+    idx = np.arange(G, dtype=np.int32)
+    gates_np = np.stack([np.zeros(G, np.int32), 2 * idx, 2 * idx + 1,
+                         np.zeros(G, np.int32), 2 * G + idx], axis=1)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = cggi.Context(p, cggi.to_device(bsk, dev), cggi.to_device(ksk, dev),
+                       forms=forms)
+    ctx.reserve(G)
+    gates = cggi.to_device(gates_np.astype(np.int32), dev)
+    wires = cggi.to_device(wires_np, dev)
+    stream = torch.cuda.current_stream()
+
+    res = {}
+    outs = {}
+    for form in forms:
+        log(f"[bench] form={form}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            ctx.eval_level(form, gates, wires)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        for _ in range(args.steps):
+            ctx.eval_level(form, gates, wires)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / args.steps
+        bs_ms, bs_n, ks_ms, ks_n = ctx.profile_read()
+        ctx.profile(False)
+        outs[form] = cggi.to_host(wires[2 * G:])
+        res[form] = dict(ms_per_step=ms, bs_kernel_ms=bs_ms / max(bs_n, 1),
+                         ks_kernel_ms=ks_ms / max(ks_n, 1),
+                         bootstraps_per_s=G * 1000.0 / ms)
+        log(f"[bench] form={form}: {ms:.3f} ms/step, bootstrap kernel "
+            f"{res[form]['bs_kernel_ms']:.3f} ms, key switch "
+            f"{res[form]['ks_kernel_ms']:.3f} ms")
+    forms_agree = (len(outs) < 2 or
+                   all(np.array_equal(outs[forms[0]], outs[f]) for f in forms))
+
+    main_form = "int8" if "int8" in res else forms[0]
+    r = res[main_form]
+    ops = int8_ops_per_bootstrap(p) * G
+    if main_form == "int8":
+        achieved = ops / (r["bs_kernel_ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 1),
+                "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+                "frac": round(achieved / PEAK_INT8_TOPS, 4), "traffic": None,
+                "kernel": "k_bootstrap_int8<1024>",
+                "per_launch": f"{G} bootstraps x {int8_ops_per_bootstrap(p):.4g}"
+                              " int8 ops"}
+    else:
+        mm = ntt_mulmods_per_bootstrap(p) * G
+        achieved = mm / (r["bs_kernel_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_MULMOD_T, "unit": "Tmulmod/s",
+                "frac": round(achieved / PEAK_MULMOD_T, 4), "traffic": None,
+                "kernel": "k_bootstrap_ntt<1024>"}
+
+    line = {
+        "metric": METRIC, "value": round(r["bootstraps_per_s"], 1),
+        "unit": "bootstraps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int8" if main_form == "int8" else "u64",
+        "data": "synthetic",
+        "config": {"workload": f"one level of {G} independent NAND gates, "
+                               "n=630 N=1024 Bg=2^7 l=3 KS base 2^2 t=8",
+                   "form": main_form, "batch": G, "gates_per_step": G,
+                   "bootstraps_per_step": G},
+        "roofline": roof,
+    }
+    if "ntt" in res and main_form != "ntt":
+        rn = res["ntt"]
+        mm = ntt_mulmods_per_bootstrap(p) * G
+        ach = mm / (rn["bs_kernel_ms"] * 1e-3) / 1e12
+        line["ntt_form"] = {
+            "value": round(rn["bootstraps_per_s"], 1),
+            "ms_per_step": round(rn["ms_per_step"], 4),
+            "roofline": {"bound": "alu", "achieved": round(ach, 3),
+                         "peak": PEAK_MULMOD_T, "unit": "Tmulmod/s",
+                         "frac": round(ach / PEAK_MULMOD_T, 4),
+                         "kernel": "k_bootstrap_ntt<1024>"}}
+        line["int8_over_ntt"] = round(r["bootstraps_per_s"] /
+                                      rn["bootstraps_per_s"], 3)
+    line["forms_bit_identical"] = bool(forms_agree)
+    line["kernel_ms"] = {f: {"bootstrap": round(v["bs_kernel_ms"], 4),
+                             "keyswitch": round(v["ks_kernel_ms"], 4)}
+                         for f, v in res.items()}
+
+    if args.cpu_sample > 0:
+        try:
+            threads = len(os.sched_getaffinity(0))
+        except AttributeError:
+            threads = os.cpu_count() or 1
+        threads = max(1, min(16, threads))
+        sample = min(G, max(args.cpu_sample, threads))
+        log(f"[bench] cpu baseline: oracle on {sample} gates, {threads} "
+            "threads")
+        rate, wall, ok = cpu_baseline(p, bsk, ksk, wires_np, gates_np,
+                                      outs[main_form], sample, threads)
+        line["cpu_baseline"] = {
+            "value": round(rate, 3), "unit": "bootstraps/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {sample} of the {G} NAND gates (pre-op, "
+                      f"bootstrap, key switch each), {wall:.1f} s wall",
+            "gpu_outputs_match": bool(ok)}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

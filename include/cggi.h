@@ -147,6 +147,16 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
                     const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
                     int32_t W, void *stream);
 
+/* Kernel timing (tracing for benchmarks).  While enabled, every bootstrap
+ * and key-switch kernel launched eagerly (not under graph capture) through
+ * this context is bracketed by HIP events recorded on the stream it is
+ * launched on.  cggi_ctx_profile_read waits for those events, returns the
+ * summed milliseconds and launch counts of each kind (any output pointer
+ * may be NULL) and clears them.  Enabling or disabling also clears. */
+int cggi_ctx_profile(cggi_ctx *ctx, int enable);
+int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
+                          double *ks_ms, int32_t *ks_launches);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);
 

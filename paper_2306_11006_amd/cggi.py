@@ -26,7 +26,8 @@ OPCODES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "MUX": 4, "NOT": 5,
 
 EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
-           "cggi_eval_level", "cggi_last_error"]
+           "cggi_eval_level", "cggi_ctx_profile", "cggi_ctx_profile_read",
+           "cggi_last_error"]
 
 
 class CggiError(RuntimeError):
@@ -63,6 +64,9 @@ def lib():
                                            vp]
         L.cggi_keyswitch_batch.argtypes = [vp, vp, vp, i32, vp]
         L.cggi_eval_level.argtypes = [vp, ctypes.c_int, vp, i32, vp, i32, vp]
+        L.cggi_ctx_profile.argtypes = [vp, ctypes.c_int]
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)
+        L.cggi_ctx_profile_read.argtypes = [vp, dp, ip, dp, ip]
         L.cggi_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -145,6 +149,19 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def profile(self, enable=True):
+        _check(lib().cggi_ctx_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """(bootstrap ms, bootstrap launches, key-switch ms, key-switch
+        launches) summed since the last read."""
+        bm, km = ctypes.c_double(), ctypes.c_double()
+        bn, kn = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().cggi_ctx_profile_read(self._h, ctypes.byref(bm),
+                                           ctypes.byref(bn), ctypes.byref(km),
+                                           ctypes.byref(kn)))
+        return bm.value, bn.value, km.value, kn.value
 
     def reserve(self, max_gates):
         _check(lib().cggi_ctx_reserve(self._h, int(max_gates)))

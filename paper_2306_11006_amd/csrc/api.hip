@@ -122,6 +122,8 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->ws_big);
     (void)hipFree(c->ws_slot);
     (void)hipFree(c->ws_count);
+    for (hipEvent_t e : c->ev_pool)
+        (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -151,6 +153,38 @@ static int reserve(Ctx *c, int32_t G, hipStream_t s)
         return set_error(CGGI_E_NOMEM, "hipMalloc of the level workspace");
     c->ws_gates = G;
     return CGGI_OK;
+}
+
+ProfScope::ProfScope(Ctx *c, int kind, hipStream_t s) : c_(c), s_(s)
+{
+    if (!c_->prof)
+        return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return;
+    while (c_->ev_pool.size() < c_->ev_used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+        c_->ev_pool.push_back(e);
+    }
+    idx_ = (long)c_->ev_used;
+    c_->ev_used += 2;
+    c_->ev_marks.push_back({kind, (size_t)idx_});
+    (void)hipEventRecord(c_->ev_pool[idx_], s_);
+}
+
+ProfScope::~ProfScope()
+{
+    if (idx_ >= 0)
+        (void)hipEventRecord(c_->ev_pool[idx_ + 1], s_);
+}
+
+static void prof_clear(Ctx *c)
+{
+    c->ev_used = 0;
+    c->ev_marks.clear();
 }
 
 } // namespace cggi
@@ -262,6 +296,7 @@ int cggi_bootstrap_batch(cggi_ctx *ctx, cggi_form_t form,
     if (rc)
         return rc;
     hipStream_t s = (hipStream_t)stream;
+    ProfScope ps(ctx, 0, s);
     return form == CGGI_FORM_INT8
                ? int8_bootstrap(ctx, d_in, d_testv, d_out, B, nullptr, s)
                : ntt_bootstrap(ctx, d_in, d_testv, d_out, B, nullptr, s);
@@ -286,6 +321,7 @@ int cggi_keyswitch_batch(cggi_ctx *ctx, const uint32_t *d_in,
     int rc = check_device(ctx);
     if (rc)
         return rc;
+    ProfScope ps(ctx, 1, (hipStream_t)stream);
     return keyswitch_launch(ctx, d_in, d_out, B, (hipStream_t)stream);
 }
 
@@ -316,6 +352,42 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
     if ((rc = reserve(ctx, G, s)))
         return rc;
     return level_launch(ctx, form, d_gates, G, d_wires, W, s);
+}
+
+int cggi_ctx_profile(cggi_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    ctx->prof = enable != 0;
+    prof_clear(ctx);
+    return CGGI_OK;
+}
+
+int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
+                          double *ks_ms, int32_t *ks_launches)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    double ms[2] = {0.0, 0.0};
+    int32_t cnt[2] = {0, 0};
+    for (const auto &m : ctx->ev_marks) {
+        hipEvent_t a = ctx->ev_pool[m.second], b = ctx->ev_pool[m.second + 1];
+        CGGI_HIP_TRY(hipEventSynchronize(b));
+        float t = 0.f;
+        CGGI_HIP_TRY(hipEventElapsedTime(&t, a, b));
+        ms[m.first] += t;
+        cnt[m.first] += 1;
+    }
+    prof_clear(ctx);
+    if (bs_ms)
+        *bs_ms = ms[0];
+    if (bs_launches)
+        *bs_launches = cnt[0];
+    if (ks_ms)
+        *ks_ms = ms[1];
+    if (ks_launches)
+        *ks_launches = cnt[1];
+    return CGGI_OK;
 }
 
 const char *cggi_last_error(void)

@@ -339,25 +339,47 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
                 int gl = (ct0 + t) * GPT + colg;
                 db[t] = dig + ((size_t)(gl * R + kb) * 2) * N + hh * (NB * 16);
             }
-            for (int dl = 0; dl < NB; ++dl) {
+            // operands of block offset dl: 4 limb rows of the Toeplitz
+            // window (A) and the sign-rotated digit blocks of both tiles (B);
+            // the next offset's operands are read before this one's MFMAs
+            // are issued, so LDS latency hides behind the matrix cores.
+            auto load_ops = [&](int dl, v4i (&af)[4], v4i (&bf)[2]) {
                 const int Mb = (J - dl) & (NB - 1);
                 const int sg = J < dl ? N : 0;
-                v4i bfr[2];
 #pragma unroll
                 for (int t = 0; t < 2; ++t)
-                    bfr[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
+                    bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t *ap = eb + q * (4 * CLEN) + 8 * dl;
-                    v4i afr;
-                    afr[0] = (int)ap[0];
-                    afr[1] = (int)ap[1];
-                    afr[2] = (int)ap[2];
-                    afr[3] = (int)ap[3];
+                    af[q][0] = (int)ap[0];
+                    af[q][1] = (int)ap[1];
+                    af[q][2] = (int)ap[2];
+                    af[q][3] = (int)ap[3];
+                }
+            };
+            v4i acur[4], bcur[2];
+            load_ops(0, acur, bcur);
+#pragma unroll
+            for (int dl = 0; dl < NB; ++dl) {
+                v4i anxt[4], bnxt[2];
+                if (dl + 1 < NB)
+                    load_ops(dl + 1, anxt, bnxt);
+                // keep the scheduler from sinking those reads below the MFMAs
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            afr, bfr[t], Cacc[t][q], 0, 0, 0);
+                            acur[q], bcur[t], Cacc[t][q], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (dl + 1 < NB) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acur[q] = anxt[q];
+                    bcur[0] = bnxt[0];
+                    bcur[1] = bnxt[1];
                 }
             }
             if (st + 1 < n * R)

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/cggi.h"
 
@@ -43,6 +44,11 @@ struct cggi_ctx {
     uint32_t *ws_big = nullptr;   // [2G][N+1] bootstrap outputs
     int32_t *ws_slot = nullptr;   // [G] first slot of each gate (-1: none)
     int32_t *ws_count = nullptr;  // [1] number of bootstrap slots
+    // kernel timing (cggi_ctx_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::pair<int, size_t>> ev_marks; // (kind, first event)
 };
 
 namespace cggi {
@@ -78,6 +84,19 @@ int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
 // (MUX combine); the plain batch call passes null maps.
 int keyswitch_launch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
                      hipStream_t s);
+
+// Brackets one kernel launch with profiling events when enabled and the
+// stream is not capturing.  kind: 0 = bootstrap, 1 = key switch.
+class ProfScope {
+  public:
+    ProfScope(Ctx *c, int kind, hipStream_t s);
+    ~ProfScope();
+
+  private:
+    Ctx *c_;
+    hipStream_t s_;
+    long idx_ = -1;
+};
 
 int level_launch(Ctx *c, cggi_form_t form, const cggi_gate_t *gates, int G,
                  uint32_t *wires, int W, hipStream_t s);

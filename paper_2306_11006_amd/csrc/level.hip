@@ -162,13 +162,18 @@ int level_launch(Ctx *c, cggi_form_t form, const cggi_gate_t *gates, int G,
     hipLaunchKernelGGL(k_level_preop, dim3(G), dim3(256), 0, s, gates,
                        c->ws_slot, wires, c->ws_small, W, sh.n);
     CGGI_HIP_TRY(hipGetLastError());
-    int rc = form == CGGI_FORM_INT8
+    int rc;
+    {
+        ProfScope ps(c, 0, s);
+        rc = form == CGGI_FORM_INT8
                  ? int8_bootstrap(c, c->ws_small, nullptr, c->ws_big, 2 * G,
                                   c->ws_count, s)
                  : ntt_bootstrap(c, c->ws_small, nullptr, c->ws_big, 2 * G,
                                  c->ws_count, s);
+    }
     if (rc != CGGI_OK)
         return rc;
+    ProfScope ps(c, 1, s);
     return keyswitch_level(c, gates, c->ws_slot, c->ws_big, wires, G, W, s);
 }
 

@@ -25,7 +25,7 @@ def test_library_exports_every_declared_function():
     L = cggi.lib()
     for name in names:
         assert hasattr(L, name), name
-    assert sorted(cggi.EXPORTS) == names
+    assert sorted(cggi.EXPORTS) == names, (sorted(cggi.EXPORTS), names)
 
 
 @pytest.mark.parametrize("p", [params.TOY, params.DEFAULT, params.LARGE])
