@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16,
                     help="gates the oracle runs for the CPU baseline (0: skip)")
     ap.add_argument("--seed", type=int, default=2306)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first "
+                         "(reference kernel for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,6 +117,13 @@ def main():
     gates = cggi.to_device(gates_np.astype(np.int32), dev)
     wires = cggi.to_device(wires_np, dev)
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mb > 0:
+        nel = args.calib_copy_mb * (1 << 20) // 4
+        a = torch.empty(nel, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     res = {}
     outs = {}

@@ -45,7 +45,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int I8_THREADS = 256;
+constexpr int I8_THREADS = 512;   // 8 waves: two per SIMD
 constexpr int OFFSET = 64;      // digit operand bias
 
 template <int N> struct I8Cfg {
@@ -55,7 +55,12 @@ template <int N> struct I8Cfg {
     static constexpr int ELEN = N + 64;        // bytes per limb window
     static constexpr int EW = ELEN / 4;        // dwords per limb window
     static constexpr int CW = N / 4 + 8;       // dwords of a shifted copy used
-    static constexpr int CLEN = N / 4 + 16;    // stride of a shifted copy
+    // stride of a shifted copy: = 8 (mod 32) dwords, so the 48 distinct
+    // dwords one Toeplitz-row read touches fall in distinct LDS banks
+    static constexpr int CLEN = N / 4 + 8;
+    // accumulator rows are padded by one dword per 32 coefficients (stride
+    // 33 between the blocks the fold writes from 32 lanes at once)
+    static constexpr int AST = N + N / 32;
     static constexpr int ECOP_DW = 2 * 2 * 4 * 4 * CLEN; // 2 buf, c', q, sigma
 };
 
@@ -152,30 +157,36 @@ template <int N>
 struct I8Smem {
     using C = I8Cfg<N>;
     static constexpr size_t ecop = (size_t)C::ECOP_DW * 4;
-    static constexpr size_t acc = (size_t)C::GPW * 2 * N * 4;
+    static constexpr size_t acc = (size_t)C::GPW * 2 * C::AST * 4;
     static size_t dig(int R) { return (size_t)C::GPW * R * 2 * N; }
     static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
     static size_t total(int R, int n) { return ecop + acc + dig(R) + ms(n); }
 };
 
-template <int N>
+// L (gadget levels) and S (sub-digits per digit) are compile-time so the
+// digit loops unroll; L = 0 selects a generic build that reads l and S at
+// run time.
+template <int N, int L, int S>
 __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
     const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
-    int n, int beta, int l, int S)
+    int n, int beta, int l_rt, int S_rt)
 {
     using C = I8Cfg<N>;
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW;
-    constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW;
+    constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW, AST = C::AST;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
-    const int R = 2 * l * S;
+    const int l = L ? L : l_rt;
+    const int SS = L ? S : S_rt;
+    const int R = 2 * l * SS;
 
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);
-    uint32_t *acc = ecop + C::ECOP_DW;                       // [GPW][2][N]
-    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * 2 * N);
+    uint32_t *acc = ecop + C::ECOP_DW;                       // [GPW][2][AST]
+    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * 2 * AST);
     uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPW * R * 2 * N);
+    auto ap = [](int j) { return j + (j >> 5); };            // padded index
 
     int count = B;
     if (d_count)
@@ -208,12 +219,15 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
             t -= N;
             v = 0u - v;
         }
-        acc[(gl * 2 + 0) * N + t] = 0u;
-        acc[(gl * 2 + 1) * N + t] = v;
+        acc[(gl * 2 + 0) * AST + ap(t)] = 0u;
+        acc[(gl * 2 + 1) * AST + ap(t)] = v;
     }
 
     // ---- key-window staging ----------------------------------------------
-    // stage st = i*R + kb uses buffer st & 1; item = (array c'*4+q, word w)
+    // stage st = i*R + kb uses buffer st & 1; item = (array c'*4+q, word w).
+    // The global reads of the next stage are issued when a stage starts and
+    // their four byte-shifted LDS copies are written between the stage's
+    // MFMA groups.
     constexpr int ITEMS = 8 * CW;
     constexpr int PER_T = (ITEMS + I8_THREADS - 1) / I8_THREADS;
     uint32_t pre_lo[PER_T], pre_hi[PER_T];
@@ -230,28 +244,35 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
             }
         }
     };
-    auto stash = [&](int buf) {
-        uint32_t *dst = ecop + buf * (2 * 4 * 4 * CLEN);
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k) {
-            int item = tid + k * I8_THREADS;
-            if (item < ITEMS) {
-                int arr = item / CW, w = item - arr * CW;
-                uint32_t *d = dst + arr * 4 * CLEN + w;
-                d[0] = pre_lo[k];
-                d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
-                d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
-                d[3 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
-            }
+    auto stash_one = [&](int buf, int k) {
+        int item = tid + k * I8_THREADS;
+        if (item < ITEMS) {
+            int arr = item / CW, w = item - arr * CW;
+            uint32_t *d = ecop + buf * (2 * 4 * 4 * CLEN) + arr * 4 * CLEN + w;
+            d[0] = pre_lo[k];
+            d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
+            d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
+            d[3 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
         }
     };
+    auto stash_dyn = [&](int buf, int k) {
+#pragma unroll
+        for (int kk = 0; kk < PER_T; ++kk)
+            if (kk == k)
+                stash_one(buf, kk);
+    };
     prefetch(0);
-    stash(0);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+        stash_one(0, k);
     __syncthreads();
 
     // ---- per-lane constants ----------------------------------------------
+    // waves w and w + 4 share a task and split the block offsets (even/odd);
+    // their partial sums meet in the fold
     const int cp = wave & 1;                 // output component of this wave
-    const int ct0 = 2 * (wave >> 1);         // first of its two column tiles
+    const int ct0 = 2 * ((wave >> 1) & 1);   // first of its two column tiles
+    const int half = wave >> 2;              // parity of its block offsets
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
@@ -266,15 +287,24 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
     const int32_t bhalf = 1 << (beta - 1);
 
     v16i Cacc[2][4];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int v = 0; v < 16; ++v)
-                Cacc[t][q][v] = 0;
 
     for (int i = 0; i < n; ++i) {
+        // The offset correction of this step enters as the starting value
+        // of the limb-0 accumulators (negated; int32 accumulation wraps mod
+        // 2^32, like the fold).  It is read here so the rotation phase hides
+        // the latency, and it is dead once the first MFMA group has run.
+        v16i c0init;
+        {
+            const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N + 32 * J + 4 * hh;
+#pragma unroll
+            for (int a4 = 0; a4 < 4; ++a4) {
+                uint4 c4 = *reinterpret_cast<const uint4 *>(cr + 8 * a4);
+                c0init[4 * a4 + 0] = half ? 0 : -(int)c4.x;
+                c0init[4 * a4 + 1] = half ? 0 : -(int)c4.y;
+                c0init[4 * a4 + 2] = half ? 0 : -(int)c4.z;
+                c0init[4 * a4 + 3] = half ? 0 : -(int)c4.w;
+            }
+        }
         __syncthreads();   // ACC of the previous step complete
         // ---- rotate, subtract, decompose into digit operands --------------
         for (int item = tid; item < GPW * 2 * (N / 4); item += I8_THREADS) {
@@ -283,44 +313,51 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
             int c = rem / (N / 4);
             int m0 = 4 * (rem - c * (N / 4));
             int e = ms[gl * (n + 1) + i];
-            const uint32_t *a = acc + (gl * 2 + c) * N;
+            const uint32_t *a = acc + (gl * 2 + c) * AST;
+            const int pm0 = ap(m0);           // the quad stays in one block
             uint32_t w4[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                int m = m0 + k;
-                int t = (m - e) & (2 * N - 1);
-                uint32_t rot = t < N ? a[t] : 0u - a[t - N];
-                w4[k] = rot - a[m] + dig_off;
+                int t = (m0 + k - e) & (2 * N - 1);
+                uint32_t rv = a[ap(t & (N - 1))];
+                rv = t >= N ? 0u - rv : rv;
+                w4[k] = rv - a[pm0 + k] + dig_off;
             }
             // byte b of the dword holds coefficient m0 + 3 - b (reversed kappa)
             int kap0 = m0 & 31, M = m0 >> 5;
             int kp = 28 - kap0;                 // kappa' of byte 0
             int off = (kp >> 4) * (NB * 16) + M * 16 + (kp & 15);
-            for (int p = 1; p <= l; ++p) {
+            int8_t *gbase = dig + (size_t)gl * R * 2 * N + off;
+#pragma unroll
+            for (int p = 1; p <= (L ? L : 8); ++p) {
+                if (!L && p > l)
+                    break;
                 int32_t d[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
                     d[k] = (int32_t)((w4[k] >> (32 - p * beta)) & bmask) - bhalf;
-                for (int s = 0; s < S; ++s) {
-                    uint32_t pos = 0, neg = 0;
+#pragma unroll
+                for (int s = 0; s < (L ? S : 2); ++s) {
+                    if (!L && s >= SS)
+                        break;
+                    uint32_t pos = 0;
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
                         int32_t sd;
-                        if (s == S - 1) {
+                        if (s == SS - 1) {
                             sd = d[k];
                         } else {
                             sd = ((d[k] + 64) & 127) - 64;
                             d[k] = (d[k] - sd) >> 7;
                         }
-                        uint32_t bp = (uint32_t)(sd + OFFSET) & 0xFFu;
-                        uint32_t bn = (uint32_t)(-(sd + OFFSET)) & 0xFFu;
-                        pos |= bp << (8 * (3 - k));
-                        neg |= bn << (8 * (3 - k));
+                        pos |= ((uint32_t)(sd + OFFSET) & 0xFFu) << (8 * (3 - k));
                     }
-                    int kb = ((c * l) + (p - 1)) * S + s;
-                    int8_t *base = dig + ((size_t)(gl * R + kb) * 2) * N;
-                    *reinterpret_cast<uint32_t *>(base + off) = pos;
-                    *reinterpret_cast<uint32_t *>(base + N + off) = neg;
+                    // bytes are in [0, 128): negate all four at once
+                    uint32_t neg = (0x80808080u - pos) ^ 0x80808080u;
+                    int kb = ((c * l) + (p - 1)) * SS + s;
+                    int8_t *base = gbase + (size_t)kb * 2 * N;
+                    *reinterpret_cast<uint32_t *>(base) = pos;
+                    *reinterpret_cast<uint32_t *>(base + N) = neg;
                 }
             }
         }
@@ -329,7 +366,8 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
         // ---- K loop: digit polynomials x block offsets --------------------
         for (int kb = 0; kb < R; ++kb) {
             const int st = i * R + kb;
-            if (st + 1 < n * R)
+            const bool more = st + 1 < n * R;
+            if (more)
                 prefetch(st + 1);
             const uint32_t *eb = ecop + (st & 1) * (2 * 4 * 4 * CLEN) +
                                  cp * (4 * 4 * CLEN) + a_lane;
@@ -340,9 +378,7 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
                 db[t] = dig + ((size_t)(gl * R + kb) * 2) * N + hh * (NB * 16);
             }
             // operands of block offset dl: 4 limb rows of the Toeplitz
-            // window (A) and the sign-rotated digit blocks of both tiles (B);
-            // the next offset's operands are read before this one's MFMAs
-            // are issued, so LDS latency hides behind the matrix cores.
+            // window (A) and the sign-rotated digit blocks of both tiles (B)
             auto load_ops = [&](int dl, v4i (&af)[4], v4i (&bf)[2]) {
                 const int Mb = (J - dl) & (NB - 1);
                 const int sg = J < dl ? N : 0;
@@ -351,48 +387,60 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const uint32_t *ap = eb + q * (4 * CLEN) + 8 * dl;
-                    af[q][0] = (int)ap[0];
-                    af[q][1] = (int)ap[1];
-                    af[q][2] = (int)ap[2];
-                    af[q][3] = (int)ap[3];
+                    const uint32_t *apq = eb + q * (4 * CLEN) + 8 * dl;
+                    af[q][0] = (int)apq[0];
+                    af[q][1] = (int)apq[1];
+                    af[q][2] = (int)apq[2];
+                    af[q][3] = (int)apq[3];
                 }
             };
-            v4i acur[4], bcur[2];
-            load_ops(0, acur, bcur);
+            constexpr int ND = NB / 2;    // block offsets per wave
+            constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
+            if (kb == 0) {
+                // first group of the step: accumulators start from the
+                // correction (limb 0) and zero (limbs 1..3)
+                v4i af[4], bf[2];
+                load_ops(half, af, bf);
+                const v16i zero = {};
 #pragma unroll
-            for (int dl = 0; dl < NB; ++dl) {
-                v4i anxt[4], bnxt[2];
-                if (dl + 1 < NB)
-                    load_ops(dl + 1, anxt, bnxt);
-                // keep the scheduler from sinking those reads below the MFMAs
-                __builtin_amdgcn_sched_barrier(0);
+                for (int t = 0; t < 2; ++t) {
+                    Cacc[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        af[0], bf[t], c0init, 0, 0, 0);
+#pragma unroll
+                    for (int q = 1; q < 4; ++q)
+                        Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            af[q], bf[t], zero, 0, 0, 0);
+                }
+                if (more && STASH0 == 0)
+                    stash_dyn((st + 1) & 1, 0);
+            }
+#pragma unroll 2
+            for (int d0 = kb == 0 ? 1 : 0; d0 < ND; ++d0) {
+                v4i af[4], bf[2];
+                load_ops(2 * d0 + half, af, bf);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int t = 0; t < 2; ++t)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            acur[q], bcur[t], Cacc[t][q], 0, 0, 0);
-                __builtin_amdgcn_sched_barrier(0);
-                if (dl + 1 < NB) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        acur[q] = anxt[q];
-                    bcur[0] = bnxt[0];
-                    bcur[1] = bnxt[1];
-                }
+                            af[q], bf[t], Cacc[t][q], 0, 0, 0);
+                // spread the next stage's LDS copies between MFMA groups
+                if (more && d0 >= STASH0 && d0 - STASH0 < PER_T)
+                    stash_dyn((st + 1) & 1, d0 - STASH0);
             }
-            if (st + 1 < n * R)
-                stash((st + 1) & 1);
+            if (ND < PER_T + 4 && more) {
+                // small N: fewer MFMA groups than copy items
+                for (int k = ND - STASH0; k < PER_T; ++k)
+                    stash_dyn((st + 1) & 1, k);
+            }
             __syncthreads();
         }
 
         // ---- fold limbs, subtract the offset correction, add into ACC -----
-        const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             int gl = (ct0 + t) * GPT + colg;
-            uint32_t *a = acc + (gl * 2 + cp) * N + 32 * J;
+            uint32_t *a = acc + (gl * 2 + cp) * AST + 33 * J;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 int row = 8 * (v >> 2) + 4 * hh + (v & 3);
@@ -400,10 +448,8 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
                              ((uint32_t)Cacc[t][1][v] << 8) +
                              ((uint32_t)Cacc[t][2][v] << 16) +
                              ((uint32_t)Cacc[t][3][v] << 24);
-                a[row] += x - cr[32 * J + row];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    Cacc[t][q][v] = 0;
+                // both waves of the pair add (mod 2^32, order-free)
+                atomicAdd(&a[row], x);
             }
         }
     }
@@ -415,14 +461,14 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
         int g = g0 + gl;
         if (g >= count)
             continue;
-        const uint32_t *a = acc + gl * 2 * N;
+        const uint32_t *a = acc + gl * 2 * AST;
         uint32_t v;
         if (j == 0)
             v = a[0];
         else if (j < N)
-            v = 0u - a[N - j];
+            v = 0u - a[ap(N - j)];
         else
-            v = a[N];
+            v = a[AST];
         out[(size_t)g * (N + 1) + j] = v;
     }
 }
@@ -475,10 +521,10 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
     }
 }
 
-template <int N>
-static int launch_bs_int8(const Ctx *c, const uint32_t *in,
-                          const uint32_t *testv, uint32_t *out, int B,
-                          const int32_t *d_count, hipStream_t s)
+template <int N, int L, int S>
+static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
+                            const uint32_t *testv, uint32_t *out, int B,
+                            const int32_t *d_count, hipStream_t s)
 {
     using C = I8Cfg<N>;
     const Shape &sh = c->sh;
@@ -486,16 +532,30 @@ static int launch_bs_int8(const Ctx *c, const uint32_t *in,
     static bool attr_done = false;
     if (!attr_done) {
         CGGI_HIP_TRY(hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_bootstrap_int8<N>),
+            reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S>),
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_done = true;
     }
     int grid = (B + C::GPW - 1) / C::GPW;
-    hipLaunchKernelGGL(k_bootstrap_int8<N>, dim3(grid), dim3(I8_THREADS),
-                       smem, s, c->bsk_i8, c->corr, in, testv, out, B,
-                       d_count, sh.n, sh.beta, sh.l, sh.S);
+    hipLaunchKernelGGL((k_bootstrap_int8<N, L, S>), dim3(grid),
+                       dim3(I8_THREADS), smem, s, c->bsk_i8, c->corr, in,
+                       testv, out, B, d_count, sh.n, sh.beta, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
+}
+
+template <int N>
+static int launch_bs_int8(const Ctx *c, const uint32_t *in,
+                          const uint32_t *testv, uint32_t *out, int B,
+                          const int32_t *d_count, hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    // specialised digit loops for the parameter sets in use, generic else
+    if (sh.l == 3 && sh.S == 1)
+        return launch_bs_int8_t<N, 3, 1>(c, in, testv, out, B, d_count, s);
+    if (sh.l == 2 && sh.S == 2)
+        return launch_bs_int8_t<N, 2, 2>(c, in, testv, out, B, d_count, s);
+    return launch_bs_int8_t<N, 0, 0>(c, in, testv, out, B, d_count, s);
 }
 
 int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
