@@ -147,6 +147,26 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
                     const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
                     int32_t W, void *stream);
 
+/* Levelise a gate DAG on the host (Section 4.2, "waves"): every gate gets
+ * level 1 + max(level of the gates producing its inputs), 0 when all its
+ * inputs are circuit inputs (wires no gate writes); gates are visited in
+ * first-in-first-out order of readiness, so the work is linear in gates
+ * plus wires and disconnected circuits are fine.  Within a level, gates are
+ * ordered by opcode (stable), the paper's per-opcode batching.
+ *   gates       HOST array [G] (only op, the used inputs and out are read)
+ *   W           number of wires; every used index must be in [0, W)
+ *   order       HOST out [G]: gate indices, level by level
+ *   level_start HOST out [G+1]: level L is order[level_start[L] ..
+ *               level_start[L+1]); *n_levels receives the level count
+ *   level       HOST out [G] or NULL: level of each gate
+ * Errors (nothing useful is written): CGGI_E_SHAPE for a bad size, NULL
+ * pointer, unknown opcode or wire out of range; CGGI_E_PARAM when two gates
+ * write the same wire, a gate writes a wire it reads, or the gates form a
+ * cycle.  Pure host code. */
+int cggi_levelize(const cggi_gate_t *gates, int32_t G, int32_t W,
+                  int32_t *order, int32_t *level_start, int32_t *n_levels,
+                  int32_t *level);
+
 /* Kernel timing (tracing for benchmarks).  While enabled, every bootstrap
  * and key-switch kernel launched eagerly (not under graph capture) through
  * this context is bracketed by HIP events recorded on the stream it is

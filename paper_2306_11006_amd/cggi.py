@@ -26,8 +26,8 @@ OPCODES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "MUX": 4, "NOT": 5,
 
 EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
-           "cggi_eval_level", "cggi_ctx_profile", "cggi_ctx_profile_read",
-           "cggi_last_error"]
+           "cggi_eval_level", "cggi_levelize", "cggi_ctx_profile",
+           "cggi_ctx_profile_read", "cggi_last_error"]
 
 
 class CggiError(RuntimeError):
@@ -64,6 +64,8 @@ def lib():
                                            vp]
         L.cggi_keyswitch_batch.argtypes = [vp, vp, vp, i32, vp]
         L.cggi_eval_level.argtypes = [vp, ctypes.c_int, vp, i32, vp, i32, vp]
+        L.cggi_levelize.argtypes = [vp, i32, i32, vp, vp,
+                                    ctypes.POINTER(i32), vp]
         L.cggi_ctx_profile.argtypes = [vp, ctypes.c_int]
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)
         L.cggi_ctx_profile_read.argtypes = [vp, dp, ip, dp, ip]
@@ -91,6 +93,24 @@ def params_check(p):
     ps = params_struct(p)
     rc = L.cggi_params_check(ctypes.byref(ps))
     return rc, (L.cggi_last_error().decode() if rc else "")
+
+
+def levelize(gates, n_wires):
+    """Host levelisation (cggi_levelize): returns (order, level_start) as
+    numpy int32 arrays; level L is gates[order[level_start[L]:
+    level_start[L+1]]]."""
+    import numpy as np
+    g = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
+    G = g.shape[0]
+    order = np.empty(G, dtype=np.int32)
+    start = np.empty(G + 1, dtype=np.int32)
+    nl = ctypes.c_int32()
+    _check(lib().cggi_levelize(g.ctypes.data_as(ctypes.c_void_p), G,
+                               int(n_wires),
+                               order.ctypes.data_as(ctypes.c_void_p),
+                               start.ctypes.data_as(ctypes.c_void_p),
+                               ctypes.byref(nl), None))
+    return order, start[: nl.value + 1].copy()
 
 
 def _ptr(t):

@@ -110,3 +110,155 @@ def random_gate_batch(seed: int, count: int, ops=("NAND", "AND", "OR", "XOR",
     gates = np.stack([op, 3 * idx, 3 * idx + 1, 3 * idx + 2,
                       3 * count + idx], axis=1).astype(np.int32)
     return gates
+
+
+class Netlist:
+    """A gate netlist under construction: wires are integers, gates append
+    in a valid sequential order (every input wire exists before the gate).
+    Gate tuples are (opcode, in0, in1, in2, out) as in cggi_gate_t."""
+
+    def __init__(self):
+        self.gates = []
+        self.n_wires = 0
+        self.input_wires = []
+
+    def inputs(self, k):
+        ids = list(range(self.n_wires, self.n_wires + k))
+        self.n_wires += k
+        self.input_wires += ids
+        return ids
+
+    def gate(self, op, a=0, b=0, c=0):
+        out = self.n_wires
+        self.n_wires += 1
+        self.gates.append((OPCODES[op], a, b, c, out))
+        return out
+
+    def array(self):
+        return np.array(self.gates, dtype=np.int32).reshape(-1, 5)
+
+
+def ripple_adder(nl, a, b):
+    """Ripple-carry adder of two little-endian bit lists: half adder on bit
+    0, then per bit p = a^b, s = p^c, carry = MUX(p, c, a).  Returns the sum
+    bits and the carry out."""
+    s = [nl.gate("XOR", a[0], b[0])]
+    c = nl.gate("AND", a[0], b[0])
+    for i in range(1, len(a)):
+        p = nl.gate("XOR", a[i], b[i])
+        s.append(nl.gate("XOR", p, c))
+        c = nl.gate("MUX", p, c, a[i])
+    return s, c
+
+
+def _full_adder_nand(nl, x, y, z):
+    """sum = x ^ y ^ z, carry = NAND(NAND(x, y), NAND(x ^ y, z))."""
+    p = nl.gate("XOR", x, y)
+    s = nl.gate("XOR", p, z)
+    c = nl.gate("NAND", nl.gate("NAND", x, y), nl.gate("NAND", p, z))
+    return s, c
+
+
+def array_multiplier(nl, a, b):
+    """Array multiplier of two n-bit little-endian operands: AND partial
+    products, then one ripple row of full adders (XOR/NAND, half adders
+    AND/XOR at the row ends) per partial-product row.  Returns 2n bits."""
+    n = len(a)
+    pp = [[nl.gate("AND", a[j], b[i]) for j in range(n)] for i in range(n)]
+    out = [pp[0][0]]
+    acc = pp[0][1:]                       # n-1 bits of weight 1..n-1
+    carry_top = None
+    for i in range(1, n):
+        row = pp[i]
+        new = []
+        c = None
+        for j in range(n):
+            x = acc[j] if j < len(acc) else carry_top
+            y = row[j]
+            if x is None:
+                s_, c_ = (y, None) if c is None else (
+                    nl.gate("XOR", y, c), nl.gate("AND", y, c))
+            elif c is None:
+                s_, c_ = nl.gate("XOR", x, y), nl.gate("AND", x, y)
+            else:
+                s_, c_ = _full_adder_nand(nl, x, y, c)
+            new.append(s_)
+            c = c_
+        out.append(new[0])
+        acc = new[1:]
+        carry_top = c
+    out += acc
+    out.append(carry_top)
+    return out
+
+
+def adder_multiplier_circuit(bits=16):
+    """The uneven-level workload: a bits-wide ripple-carry adder and a
+    bits x bits array multiplier side by side (independent operands).
+    Returns (netlist, dict of input/output wire lists)."""
+    nl = Netlist()
+    a, b = nl.inputs(bits), nl.inputs(bits)
+    x, y = nl.inputs(bits), nl.inputs(bits)
+    s, c = ripple_adder(nl, a, b)
+    p = array_multiplier(nl, x, y)
+    return nl, dict(a=a, b=b, x=x, y=y, sum=s + [c], prod=p)
+
+
+def random_dag(seed, n_gates, max_width=65536, n_inputs=64,
+               ops=("NAND", "AND", "OR", "XOR", "MUX")):
+    """Random levelled DAG: level widths log-uniform in [1, max_width] until
+    n_gates gates exist (the last level is cut to fit); every gate reads one
+    wire of the previous level and the rest uniformly from all earlier
+    wires; opcodes uniform over `ops`."""
+    g = rng(seed)
+    nl = Netlist()
+    prev = nl.inputs(n_inputs)
+    earlier = list(prev)
+    codes = list(ops)
+    while len(nl.gates) < n_gates:
+        w = int(np.exp(g.uniform(0.0, np.log(max_width))))
+        w = max(1, min(w, n_gates - len(nl.gates)))
+        ops_l = g.integers(0, len(codes), size=w)
+        first = g.integers(0, len(prev), size=w)
+        rest = g.integers(0, len(earlier), size=(w, 2))
+        cur = []
+        for k in range(w):
+            cur.append(nl.gate(codes[ops_l[k]], prev[first[k]],
+                               earlier[rest[k, 0]], earlier[rest[k, 1]]))
+        earlier += cur
+        prev = cur
+    return nl
+
+
+def eval_plain(gates, values):
+    """Evaluate a netlist on plaintext bits (dict or array indexed by wire),
+    gates in the given (sequential) order.  Boolean logic only."""
+    v = dict(values) if isinstance(values, dict) else {
+        i: int(x) for i, x in enumerate(values)}
+    for op, a, b, c, o in np.asarray(gates).tolist():
+        if op == 0:
+            r = 1 - (v[a] & v[b])
+        elif op == 1:
+            r = v[a] & v[b]
+        elif op == 2:
+            r = v[a] | v[b]
+        elif op == 3:
+            r = v[a] ^ v[b]
+        elif op == 4:
+            r = v[b] if v[a] else v[c]
+        elif op == 5:
+            r = 1 - v[a]
+        elif op == 6:
+            r = v[a]
+        elif op == 7:
+            r = 0
+        elif op == 8:
+            r = 1
+        elif op == 9:
+            r = 1 - (v[a] | v[b])
+        elif op == 10:
+            r = 1 - (v[a] ^ v[b])
+        else:
+            raise ValueError(op)
+        v[o] = r
+    return v
