@@ -78,8 +78,6 @@ static int check_form(const Shape &s, uint32_t form)
                              "NTT form: (2l+3)*N*8 + 2(n+1) bytes exceed LDS");
     }
     if (form & CGGI_FORM_INT8) {
-        if (s.N > 1024)
-            return set_error(CGGI_E_PARAM, "INT8 form: N > 1024 not built");
         if (s.S == 0)
             return set_error(CGGI_E_PARAM, "INT8 form: bg_bit must be <= 13");
         if (int8_smem_bytes(s.N, s.R, s.n) > LDS_BYTES)

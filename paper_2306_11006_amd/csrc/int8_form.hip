@@ -45,13 +45,21 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int I8_THREADS = 512;   // 8 waves: two per SIMD
 constexpr int OFFSET = 64;      // digit operand bias
 
+// N <= 1024: a workgroup owns 4 column tiles (4 * 1024 / N bootstraps) and
+// runs 8 waves (two per SIMD) with double-buffered key windows.
+// N = 2048: a bootstrap spans 2 column tiles; a workgroup owns one
+// bootstrap, runs 4 waves and single-buffers the (twice as long) windows.
 template <int N> struct I8Cfg {
+    static constexpr bool BIG = N > 1024;
     static constexpr int NB = N / 32;          // blocks per polynomial
-    static constexpr int GPT = 1024 / N;       // bootstraps per column tile
-    static constexpr int GPW = 4 * GPT;        // bootstraps per workgroup
+    static constexpr int TPG = BIG ? N / 1024 : 1;  // column tiles per bootstrap
+    static constexpr int GPT = BIG ? 1 : 1024 / N;  // bootstraps per column tile
+    static constexpr int TILES = BIG ? 2 : 4;       // column tiles per workgroup
+    static constexpr int GPW = BIG ? TILES / TPG : TILES * GPT; // bootstraps
+    static constexpr int THREADS = BIG ? 256 : 512;
+    static constexpr int EBUF = BIG ? 1 : 2;   // key-window buffers
     static constexpr int ELEN = N + 64;        // bytes per limb window
     static constexpr int EW = ELEN / 4;        // dwords per limb window
     static constexpr int CW = N / 4 + 8;       // dwords of a shifted copy used
@@ -61,7 +69,7 @@ template <int N> struct I8Cfg {
     // accumulator rows are padded by one dword per 32 coefficients (stride
     // 33 between the blocks the fold writes from 32 lanes at once)
     static constexpr int AST = N + N / 32;
-    static constexpr int ECOP_DW = 2 * 2 * 4 * 4 * CLEN; // 2 buf, c', q, sigma
+    static constexpr int ECOP_DW = EBUF * 2 * 4 * 4 * CLEN; // buf, c', q, sigma
 };
 
 __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
@@ -167,14 +175,17 @@ struct I8Smem {
 // digit loops unroll; L = 0 selects a generic build that reads l and S at
 // run time.
 template <int N, int L, int S>
-__global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
+__global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
     const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
     int n, int beta, int l_rt, int S_rt)
 {
     using C = I8Cfg<N>;
-    constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW;
+    constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
+    constexpr int TILES = C::TILES, EBUF = C::EBUF;
+    constexpr bool BIG = C::BIG;
+    constexpr int I8_THREADS = C::THREADS;
     constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW, AST = C::AST;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
     const int l = L ? L : l_rt;
@@ -248,7 +259,8 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
         int item = tid + k * I8_THREADS;
         if (item < ITEMS) {
             int arr = item / CW, w = item - arr * CW;
-            uint32_t *d = ecop + buf * (2 * 4 * 4 * CLEN) + arr * 4 * CLEN + w;
+            uint32_t *d = ecop + (EBUF == 2 ? buf : 0) * (2 * 4 * 4 * CLEN) +
+                          arr * 4 * CLEN + w;
             d[0] = pre_lo[k];
             d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
             d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
@@ -268,16 +280,23 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
     __syncthreads();
 
     // ---- per-lane constants ----------------------------------------------
-    // waves w and w + 4 share a task and split the block offsets (even/odd);
-    // their partial sums meet in the fold
-    const int cp = wave & 1;                 // output component of this wave
-    const int ct0 = 2 * ((wave >> 1) & 1);   // first of its two column tiles
-    const int half = wave >> 2;              // parity of its block offsets
+    // waves w and w + TILES share a task and split the block offsets
+    // (even/odd); their partial sums meet in the fold
+    const int cp = wave & 1;                         // output component
+    const int ct0 = 2 * ((wave >> 1) % (TILES / 2)); // first of two tiles
+    const int half = wave / TILES;                   // block-offset parity
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
-    // B operand: column c -> bootstrap (within tile) and output block J
-    const int colg = rho / NB, J = rho % NB;
+    // B operand: column c of tile t -> bootstrap in the workgroup and
+    // output block J of that bootstrap
+    int glt[2], Jt[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int T = ct0 + t;
+        glt[t] = BIG ? T / TPG : T * GPT + rho / NB;
+        Jt[t] = BIG ? 32 * (T % TPG) + rho : rho % NB;
+    }
 
     const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
     uint32_t dig_off = round_off;
@@ -293,16 +312,19 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
         // of the limb-0 accumulators (negated; int32 accumulation wraps mod
         // 2^32, like the fold).  It is read here so the rotation phase hides
         // the latency, and it is dead once the first MFMA group has run.
-        v16i c0init;
-        {
-            const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N + 32 * J + 4 * hh;
+        constexpr int NCI = BIG ? 2 : 1;   // tiles of one bootstrap differ
+        v16i c0init[NCI];
+#pragma unroll
+        for (int t = 0; t < NCI; ++t) {
+            const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N + 32 * Jt[t] +
+                                 4 * hh;
 #pragma unroll
             for (int a4 = 0; a4 < 4; ++a4) {
                 uint4 c4 = *reinterpret_cast<const uint4 *>(cr + 8 * a4);
-                c0init[4 * a4 + 0] = half ? 0 : -(int)c4.x;
-                c0init[4 * a4 + 1] = half ? 0 : -(int)c4.y;
-                c0init[4 * a4 + 2] = half ? 0 : -(int)c4.z;
-                c0init[4 * a4 + 3] = half ? 0 : -(int)c4.w;
+                c0init[t][4 * a4 + 0] = half ? 0 : -(int)c4.x;
+                c0init[t][4 * a4 + 1] = half ? 0 : -(int)c4.y;
+                c0init[t][4 * a4 + 2] = half ? 0 : -(int)c4.z;
+                c0init[t][4 * a4 + 3] = half ? 0 : -(int)c4.w;
             }
         }
         __syncthreads();   // ACC of the previous step complete
@@ -369,22 +391,23 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
             const bool more = st + 1 < n * R;
             if (more)
                 prefetch(st + 1);
-            const uint32_t *eb = ecop + (st & 1) * (2 * 4 * 4 * CLEN) +
+            const uint32_t *eb = ecop + (EBUF == 2 ? (st & 1) : 0) *
+                                            (2 * 4 * 4 * CLEN) +
                                  cp * (4 * 4 * CLEN) + a_lane;
             const int8_t *db[2];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                int gl = (ct0 + t) * GPT + colg;
-                db[t] = dig + ((size_t)(gl * R + kb) * 2) * N + hh * (NB * 16);
-            }
+            for (int t = 0; t < 2; ++t)
+                db[t] = dig + ((size_t)(glt[t] * R + kb) * 2) * N +
+                        hh * (NB * 16);
             // operands of block offset dl: 4 limb rows of the Toeplitz
             // window (A) and the sign-rotated digit blocks of both tiles (B)
             auto load_ops = [&](int dl, v4i (&af)[4], v4i (&bf)[2]) {
-                const int Mb = (J - dl) & (NB - 1);
-                const int sg = J < dl ? N : 0;
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < 2; ++t) {
+                    const int Mb = (Jt[t] - dl) & (NB - 1);
+                    const int sg = Jt[t] < dl ? N : 0;
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t *apq = eb + q * (4 * CLEN) + 8 * dl;
@@ -405,13 +428,13 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
                     Cacc[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                        af[0], bf[t], c0init, 0, 0, 0);
+                        af[0], bf[t], c0init[BIG ? t : 0], 0, 0, 0);
 #pragma unroll
                     for (int q = 1; q < 4; ++q)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                             af[q], bf[t], zero, 0, 0, 0);
                 }
-                if (more && STASH0 == 0)
+                if (EBUF == 2 && more && STASH0 == 0)
                     stash_dyn((st + 1) & 1, 0);
             }
 #pragma unroll 2
@@ -425,22 +448,28 @@ __global__ __launch_bounds__(I8_THREADS, 1) void k_bootstrap_int8(
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                             af[q], bf[t], Cacc[t][q], 0, 0, 0);
                 // spread the next stage's LDS copies between MFMA groups
-                if (more && d0 >= STASH0 && d0 - STASH0 < PER_T)
+                if (EBUF == 2 && more && d0 >= STASH0 && d0 - STASH0 < PER_T)
                     stash_dyn((st + 1) & 1, d0 - STASH0);
             }
-            if (ND < PER_T + 4 && more) {
+            if (EBUF == 2 && ND < PER_T + 4 && more) {
                 // small N: fewer MFMA groups than copy items
                 for (int k = ND - STASH0; k < PER_T; ++k)
                     stash_dyn((st + 1) & 1, k);
             }
             __syncthreads();
+            if (EBUF == 1 && more) {
+                // single window buffer: refill it once every wave is done
+#pragma unroll
+                for (int k = 0; k < PER_T; ++k)
+                    stash_one(0, k);
+                __syncthreads();
+            }
         }
 
         // ---- fold limbs, subtract the offset correction, add into ACC -----
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            int gl = (ct0 + t) * GPT + colg;
-            uint32_t *a = acc + (gl * 2 + cp) * AST + 33 * J;
+            uint32_t *a = acc + (glt[t] * 2 + cp) * AST + 33 * Jt[t];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 int row = 8 * (v >> 2) + 4 * hh + (v & 3);
@@ -481,6 +510,7 @@ size_t int8_smem_bytes(int N, int R, int n)
     case 256: return I8Smem<256>::total(R, n);
     case 512: return I8Smem<512>::total(R, n);
     case 1024: return I8Smem<1024>::total(R, n);
+    case 2048: return I8Smem<2048>::total(R, n);
     default: return (size_t)-1;
     }
 }
@@ -517,7 +547,8 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
     case 256: return make_key_n<256>(c, bsk, s);
     case 512: return make_key_n<512>(c, bsk, s);
     case 1024: return make_key_n<1024>(c, bsk, s);
-    default: return set_error(CGGI_E_PARAM, "INT8 form: N must be 256..1024");
+    case 2048: return make_key_n<2048>(c, bsk, s);
+    default: return set_error(CGGI_E_PARAM, "INT8 form: unsupported N");
     }
 }
 
@@ -538,7 +569,7 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     }
     int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8<N, L, S>), dim3(grid),
-                       dim3(I8_THREADS), smem, s, c->bsk_i8, c->corr, in,
+                       dim3(C::THREADS), smem, s, c->bsk_i8, c->corr, in,
                        testv, out, B, d_count, sh.n, sh.beta, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
@@ -566,7 +597,8 @@ int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
     case 256: return launch_bs_int8<256>(c, in, testv, out, B, d_count, s);
     case 512: return launch_bs_int8<512>(c, in, testv, out, B, d_count, s);
     case 1024: return launch_bs_int8<1024>(c, in, testv, out, B, d_count, s);
-    default: return set_error(CGGI_E_PARAM, "INT8 form: N must be 256..1024");
+    case 2048: return launch_bs_int8<2048>(c, in, testv, out, B, d_count, s);
+    default: return set_error(CGGI_E_PARAM, "INT8 form: unsupported N");
     }
 }
 

@@ -82,11 +82,14 @@ def test_create_rejects_bad_arguments_before_any_gpu_work():
     assert L.cggi_ctx_create(ctypes.byref(ps), ctypes.c_void_p(2),
                              ctypes.c_void_p(8), 1, None,
                              ctypes.byref(h)) == cggi.E_SHAPE
-    # int8 form needs N <= 1024
-    pl = cggi.params_struct(params.LARGE)
+    # int8 form splits digits into at most two 7-bit parts (Bg <= 2^13)
+    import dataclasses
+    pl = cggi.params_struct(dataclasses.replace(params.LARGE, bg_bit=14,
+                                                l=1))
     assert L.cggi_ctx_create(ctypes.byref(pl), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), 2, None,
                              ctypes.byref(h)) == cggi.E_PARAM
+    assert b"bg_bit" in L.cggi_last_error()
     assert h.value is None
 
 
