@@ -50,9 +50,25 @@ __host__ __device__ __forceinline__ uint64_t reduce128(uint64_t hi,
     return r;
 }
 
+// 64 x 64 -> 128-bit product from four 32 x 32 + 64 multiply-adds
+// (a*b and __umul64hi separately would repeat the partial products).
+__device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t &hi,
+                                       uint64_t &lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t m1 = (uint64_t)a0 * b1 + (p00 >> 32);
+    const uint64_t m2 = (uint64_t)a1 * b0 + (uint32_t)m1;
+    lo = (m2 << 32) | (uint32_t)p00;
+    hi = (uint64_t)a1 * b1 + (m1 >> 32) + (m2 >> 32);
+}
+
 __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b)
 {
-    return reduce128(__umul64hi(a, b), a * b);
+    uint64_t hi, lo;
+    mul128(a, b, hi, lo);
+    return reduce128(hi, lo);
 }
 
 inline uint64_t mul_host(uint64_t a, uint64_t b)

@@ -35,50 +35,114 @@ unsigned bitrev(unsigned x, int bits)
 }
 
 // In-place negacyclic forward NTT of P polynomials of length N in LDS
-// (Cooley-Tukey, psi-twisted, output in bit-reversed order).
+// (Cooley-Tukey with the psi-twisted twiddles tw[m + i] = psi^bitrev(m + i),
+// output in bit-reversed order).  Stages are taken NS = 3 at a time: a thread
+// loads the 2^NS elements one radix-2^NS block touches, runs the NS stages
+// in registers and stores them back, so each LDS round trip (and barrier)
+// covers three stages.
+template <int N, int NS>
+__device__ __forceinline__ void fwd_pass(uint64_t *a, int P, int s0,
+                                         const uint64_t *__restrict__ tw)
+{
+    constexpr int K = 1 << NS;
+    const int m0 = 1 << s0;                 // groups at the first stage
+    const int t0 = N >> (s0 + 1);           // half-span at the first stage
+    const int stride = (2 * t0) >> NS;      // distance between block elements
+    const int per_poly = N / K;
+    for (int idx = threadIdx.x; idx < P * per_poly; idx += NTT_THREADS) {
+        const int poly = idx / per_poly, r = idx - poly * per_poly;
+        const int i = r / stride, off = r - i * stride;
+        uint64_t *x = a + poly * N + 2 * t0 * i + off;
+        uint64_t v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            v[k] = x[k * stride];
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+            const int d = 1 << (NS - 1 - u);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k & d)
+                    continue;
+                const uint64_t S = tw[(m0 << u) + (i << u) + (k >> (NS - u))];
+                const uint64_t U = v[k], V = gl::mul(v[k + d], S);
+                v[k] = gl::add(U, V);
+                v[k + d] = gl::sub(U, V);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            x[k * stride] = v[k];
+    }
+    __syncthreads();
+}
+
 template <int N>
 __device__ __forceinline__ void ntt_fwd(uint64_t *a, int P,
                                         const uint64_t *__restrict__ tw)
 {
-    constexpr int H = N / 2;
-    int t = N;
-    for (int m = 1; m < N; m <<= 1) {
-        t >>= 1;
-        for (int idx = threadIdx.x; idx < P * H; idx += NTT_THREADS) {
-            int poly = idx / H, k = idx - poly * H;
-            int i = k / t, j = k - i * t;
-            uint64_t *x = a + poly * N + 2 * i * t + j;
-            uint64_t S = tw[m + i];
-            uint64_t U = x[0], V = gl::mul(x[t], S);
-            x[0] = gl::add(U, V);
-            x[t] = gl::sub(U, V);
-        }
-        __syncthreads();
-    }
+    constexpr int LOGN = __builtin_ctz(N);
+    int s = 0;
+    for (; s + 3 <= LOGN; s += 3)
+        fwd_pass<N, 3>(a, P, s, tw);
+    if (LOGN - s == 2)
+        fwd_pass<N, 2>(a, P, s, tw);
+    else if (LOGN - s == 1)
+        fwd_pass<N, 1>(a, P, s, tw);
 }
 
-// In-place inverse (Gentleman-Sande, bit-reversed input, natural output),
-// without the final 1/N scaling.
+// In-place inverse (Gentleman-Sande, bit-reversed input, natural output,
+// twiddles twi[h + i] = psi^-bitrev(h + i)), without the final 1/N scaling;
+// NS stages per LDS round trip as in the forward transform.
+template <int N, int NS>
+__device__ __forceinline__ void inv_pass(uint64_t *a, int P, int u0,
+                                         const uint64_t *__restrict__ twi)
+{
+    constexpr int K = 1 << NS;
+    const int t0 = 1 << u0;                 // half-span at the first stage
+    const int span = t0 * K;                // block of the pass
+    const int per_poly = N / K;
+    for (int idx = threadIdx.x; idx < P * per_poly; idx += NTT_THREADS) {
+        const int poly = idx / per_poly, r = idx - poly * per_poly;
+        const int blk = r / t0, off = r - blk * t0;
+        uint64_t *x = a + poly * N + blk * span + off;
+        uint64_t v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            v[k] = x[k * t0];
+#pragma unroll
+        for (int w = 0; w < NS; ++w) {
+            const int d = 1 << w;
+            const int h = N >> (u0 + w + 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (k & d)
+                    continue;
+                const uint64_t S = twi[h + (blk << (NS - w - 1)) + (k >> (w + 1))];
+                const uint64_t U = v[k], V = v[k + d];
+                v[k] = gl::add(U, V);
+                v[k + d] = gl::mul(gl::sub(U, V), S);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            x[k * t0] = v[k];
+    }
+    __syncthreads();
+}
+
 template <int N>
 __device__ __forceinline__ void ntt_inv(uint64_t *a, int P,
                                         const uint64_t *__restrict__ twi)
 {
-    constexpr int H = N / 2;
-    int t = 1;
-    for (int m = N; m > 1; m >>= 1) {
-        int h = m >> 1;
-        for (int idx = threadIdx.x; idx < P * H; idx += NTT_THREADS) {
-            int poly = idx / H, k = idx - poly * H;
-            int i = k / t, j = k - i * t;
-            uint64_t *x = a + poly * N + 2 * i * t + j;
-            uint64_t S = twi[h + i];
-            uint64_t U = x[0], V = x[t];
-            x[0] = gl::add(U, V);
-            x[t] = gl::mul(gl::sub(U, V), S);
-        }
-        __syncthreads();
-        t <<= 1;
-    }
+    constexpr int LOGN = __builtin_ctz(N);
+    int u = 0;
+    for (; u + 3 <= LOGN; u += 3)
+        inv_pass<N, 3>(a, P, u, twi);
+    if (LOGN - u == 2)
+        inv_pass<N, 2>(a, P, u, twi);
+    else if (LOGN - u == 1)
+        inv_pass<N, 1>(a, P, u, twi);
 }
 
 template <int N>
