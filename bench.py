@@ -41,6 +41,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_sha256(path):
+    """sha256 of a C++/HIP source with // comments and blank lines removed
+    (a comment edit does not change the kernel the counters describe)."""
+    import hashlib
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        code = line.split("//", 1)[0].strip()
+        if code:
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
+def stored_traffic(profile="profiles/eval_level_1024_nand_default.md"):
+    """HBM bytes per launch of the int8 bootstrap kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs (each scaled by the factor the same
+    counter showed for a copy of known size), or None when the counters were
+    taken on another version of the kernel source."""
+    try:
+        text = open(os.path.join(ROOT, profile)).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if line.startswith("traffic-") and ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if code_sha256(os.path.join(ROOT, kv["traffic-source"])) != \
+                kv["traffic-code-sha256"]:
+            return None
+        kib = (float(kv["traffic-fetch-kib"]) * float(kv["traffic-fetch-factor"])
+               + float(kv["traffic-write-kib"]) *
+               float(kv["traffic-write-factor"]))
+    except (KeyError, ValueError, OSError):
+        return None
+    return int(round(kib * 1024))
+
+
 def int8_ops_per_bootstrap(p):
     S = 1 if p.bg_bit <= 7 else 2
     return 2 * (2 * p.N) * (2 * p.l * p.N * S) * 4 * p.n
@@ -161,7 +199,9 @@ def main():
         achieved = ops / (r["bs_kernel_ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(achieved, 1),
                 "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                "frac": round(achieved / PEAK_INT8_TOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_INT8_TOPS, 4),
+                "traffic": stored_traffic() if G == 1024 else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
                 "kernel": "k_bootstrap_int8<1024>",
                 "per_launch": f"{G} bootstraps x {int8_ops_per_bootstrap(p):.4g}"
                               " int8 ops"}

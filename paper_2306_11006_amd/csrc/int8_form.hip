@@ -24,18 +24,23 @@
 //    sub-digits delta in [-64, 64) (one for Bg <= 2^7).  The operand holds
 //    delta + 64 in [0, 128) so that the sign flip of wrapped blocks stays in
 //    int8; the extra 64 * sum_r a_r * (1 + X + .. + X^(N-1)) is a per-step
-//    constant precomputed at context creation and subtracted in the fold.
+//    constant precomputed at context creation and entered, negated, as the
+//    starting value of the limb-0 accumulators.
 //  * Exactness: |sum| <= R*N*128*127 < 2^31, so int32 never overflows, and
 //    the recombination is a ring identity mod 2^32.
 //
-// Launch layout: 256 threads (4 waves) per workgroup, one workgroup per CU
-// (LDS-limited).  A workgroup owns 4 column tiles = 4*1024/N bootstraps.
-// Wave w computes output component c' = w & 1 for column tiles 2(w>>1) and
-// 2(w>>1)+1 with four limb accumulators each (8 x 16 int32 registers).
+// Launch layout (N <= 1024): 512 threads (8 waves, two per SIMD) per
+// workgroup, one workgroup per CU (LDS-limited); a workgroup owns 4 column
+// tiles = 4*1024/N bootstraps.  Wave w computes output component
+// c' = w & 1 for the two column tiles 2((w>>1) % 2) and 2((w>>1) % 2) + 1
+// with four limb accumulators each (8 x 16 int32 registers), over the block
+// offsets Delta of parity w / 4; the two waves of a pair add their partial
+// sums into the LDS accumulator (mod 2^32, so the order does not matter).
 // LDS holds the accumulators, the digit operands (both signs), the step's
 // key windows in four byte-shifted copies (so every lane reads its 16-byte
 // Toeplitz row as four aligned dwords), double-buffered per digit
-// polynomial, and the modulus-switched inputs.
+// polynomial, and the modulus-switched inputs.  N = 2048 runs 4 waves per
+// bootstrap with single-buffered windows (see I8Cfg).
 #include "internal.hpp"
 
 namespace cggi {

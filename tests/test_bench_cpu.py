@@ -1,0 +1,56 @@
+"""bench.py host helpers (no GPU): the operation counts behind the roofline
+figures and the stored-counter lookup behind roofline.traffic."""
+import os
+import shutil
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2306_11006_amd import params  # noqa: E402
+
+
+def test_int8_ops_default_and_large():
+    # 2 * 2N * (2lN * S) * 4 limbs * n
+    assert bench.int8_ops_per_bootstrap(params.DEFAULT) == \
+        2 * 2048 * (6 * 1024) * 4 * 630
+    assert bench.int8_ops_per_bootstrap(params.LARGE) == \
+        2 * 4096 * (4 * 2048 * 2) * 4 * 742
+
+
+def test_ntt_mulmods_default():
+    # (2l + 2) transforms of N/2 log2 N butterflies + 2l * 2N pointwise
+    assert bench.ntt_mulmods_per_bootstrap(params.DEFAULT) == \
+        630 * (8 * 512 * 10 + 6 * 2048)
+
+
+def test_code_hash_ignores_comments(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    a.write_text("int f() { return 1; }\n")
+    b.write_text("// header\n\nint f() { return 1; }  // trailing\n")
+    assert bench.code_sha256(str(a)) == bench.code_sha256(str(b))
+    b.write_text("int f() { return 2; }\n")
+    assert bench.code_sha256(str(a)) != bench.code_sha256(str(b))
+
+
+def test_stored_traffic_follows_the_source(tmp_path, monkeypatch):
+    """Counters are reported for the kernel source they were taken on and
+    dropped (None) once the code changes."""
+    prof = os.path.join(ROOT, "profiles", "eval_level_1024_nand_default.md")
+    text = open(prof).read()
+    src_rel = [ln.split(":", 1)[1].strip() for ln in text.splitlines()
+               if ln.startswith("traffic-source:")][0]
+    fake = tmp_path / "repo"
+    (fake / "profiles").mkdir(parents=True)
+    shutil.copy(prof, fake / "profiles" / os.path.basename(prof))
+    os.makedirs(fake / os.path.dirname(src_rel))
+    shutil.copy(os.path.join(ROOT, src_rel), fake / src_rel)
+    monkeypatch.setattr(bench, "ROOT", str(fake))
+    same = bench.stored_traffic()
+    with open(fake / src_rel, "a") as f:
+        f.write("\nstatic int changed_kernel_code;\n")
+    assert bench.stored_traffic() is None
+    if same is not None:   # the committed counters match the committed kernel
+        assert same > 0
