@@ -404,15 +404,8 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             for (int t = 0; t < 2; ++t)
                 db[t] = dig + ((size_t)(glt[t] * R + kb) * 2) * N +
                         hh * (NB * 16);
-            // operands of block offset dl: 4 limb rows of the Toeplitz
-            // window (A) and the sign-rotated digit blocks of both tiles (B)
-            auto load_ops = [&](int dl, v4i (&af)[4], v4i (&bf)[2]) {
-#pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    const int Mb = (Jt[t] - dl) & (NB - 1);
-                    const int sg = Jt[t] < dl ? N : 0;
-                    bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
-                }
+            // A operand of block offset dl: 4 limb rows of the Toeplitz window
+            auto load_a = [&](int dl, v4i (&af)[4]) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const uint32_t *apq = eb + q * (4 * CLEN) + 8 * dl;
@@ -422,30 +415,70 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
                     af[q][3] = (int)apq[3];
                 }
             };
-            constexpr int ND = NB / 2;    // block offsets per wave
-            constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
-            if (kb == 0) {
-                // first group of the step: accumulators start from the
-                // correction (limb 0) and zero (limbs 1..3)
-                v4i af[4], bf[2];
-                load_ops(half, af, bf);
-                const v16i zero = {};
+            // B operand of block offset dl: the sign-rotated digit blocks of
+            // both tiles
+            auto load_b = [&](int dl, v4i (&bf)[2]) {
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
-                    Cacc[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                        af[0], bf[t], c0init[BIG ? t : 0], 0, 0, 0);
+                    const int Mb = (Jt[t] - dl) & (NB - 1);
+                    const int sg = Jt[t] < dl ? N : 0;
+                    bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
+                }
+            };
+            // B of dl + 1 from B of dl: column J takes column J - 1's block
+            // with the same sign rule (J - 1 < dl iff J < dl + 1), so a
+            // one-lane shift (DPP wave_shr:1) gives every lane but the first
+            // column of each run of output blocks, which reloads its block
+            // (the one that wraps, negated) from LDS.
+            constexpr int RUN = NB < 32 ? NB : 32;   // lanes per run of blocks
+            auto next_b = [&](int dl, v4i (&bf)[2]) {
 #pragma unroll
-                    for (int q = 1; q < 4; ++q)
-                        Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[q], bf[t], zero, 0, 0, 0);
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        bf[t][k] = __builtin_amdgcn_mov_dpp(bf[t][k], 0x138, 0xF,
+                                                            0xF, true);
+                if ((rho & (RUN - 1)) == 0)
+                    load_b(dl, bf);
+            };
+            constexpr int ND = NB / 2;    // block offsets per wave
+            constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
+            // this wave's block offsets: dl0 .. dl0 + ND - 1
+            const int dl0 = half * ND;
+            v4i bf[2];
+            load_b(dl0, bf);
+            {
+                v4i af[4];
+                load_a(dl0, af);
+                if (kb == 0) {
+                    // first group of the step: accumulators start from the
+                    // correction (limb 0) and zero (limbs 1..3)
+                    const v16i zero = {};
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        Cacc[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            af[0], bf[t], c0init[BIG ? t : 0], 0, 0, 0);
+#pragma unroll
+                        for (int q = 1; q < 4; ++q)
+                            Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                af[q], bf[t], zero, 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int t = 0; t < 2; ++t)
+                            Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                af[q], bf[t], Cacc[t][q], 0, 0, 0);
                 }
                 if (EBUF == 2 && more && STASH0 == 0)
                     stash_dyn((st + 1) & 1, 0);
             }
-#pragma unroll 2
-            for (int d0 = kb == 0 ? 1 : 0; d0 < ND; ++d0) {
-                v4i af[4], bf[2];
-                load_ops(2 * d0 + half, af, bf);
+#pragma unroll 1
+            for (int d0 = 1; d0 < ND; ++d0) {
+                v4i af[4];
+                load_a(dl0 + d0, af);
+                next_b(dl0 + d0, bf);
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
