@@ -90,9 +90,12 @@ def ntt_mulmods_per_bootstrap(p):
     return p.n * ((2 * p.l + 2) * per_ntt + 2 * p.l * 2 * p.N)
 
 
-def cpu_baseline(p, bsk, ksk, wires_np, gates_np, out_gpu, sample, threads):
-    """Time the oracle on `sample` gates of the batch with `threads` host
-    threads; compare those gates' outputs with the GPU's."""
+def cpu_baseline(p, bsk, ksk, wires_np, gates_np, out_gpu, min_gates,
+                 min_seconds, threads):
+    """Time the oracle on the first gates of the batch with `threads` host
+    threads, one round of `threads` gates at a time, until at least
+    `min_gates` gates and `min_seconds` of wall time are done (or the batch
+    is exhausted); compare those gates' outputs with the GPU's."""
     import numpy as np
     import oracle as O
     O.lib()
@@ -101,14 +104,20 @@ def cpu_baseline(p, bsk, ksk, wires_np, gates_np, out_gpu, sample, threads):
         op, a, b, _, _ = gates_np[g]
         return O.gate(p, int(op), bsk, ksk, wires_np[a], wires_np[b])
 
-    idx = list(range(sample))
+    G = len(gates_np)
+    outs = []
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(threads) as ex:
-        outs = list(ex.map(one, idx))
+        while len(outs) < G:
+            done = len(outs)
+            if done >= min_gates and time.perf_counter() - t0 >= min_seconds:
+                break
+            idx = range(done, min(G, done + threads))
+            outs.extend(ex.map(one, idx))
     wall = time.perf_counter() - t0
     # out_gpu holds the output wires in gate order
-    ok = all(np.array_equal(outs[i], out_gpu[g]) for i, g in enumerate(idx))
-    return sample / wall, wall, ok
+    ok = all(np.array_equal(o, out_gpu[g]) for g, o in enumerate(outs))
+    return len(outs) / wall, len(outs), wall, ok
 
 
 def main():
@@ -119,7 +128,10 @@ def main():
     ap.add_argument("--gates", type=int, default=1024)
     ap.add_argument("--forms", default="int8,ntt")
     ap.add_argument("--cpu-sample", type=int, default=16,
-                    help="gates the oracle runs for the CPU baseline (0: skip)")
+                    help="least gates the oracle runs for the CPU baseline "
+                         "(0: skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="least wall time of the CPU baseline sample")
     ap.add_argument("--seed", type=int, default=2306)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first "
@@ -250,11 +262,11 @@ def main():
         except AttributeError:
             threads = os.cpu_count() or 1
         threads = max(1, min(16, threads))
-        sample = min(G, max(args.cpu_sample, threads))
-        log(f"[bench] cpu baseline: oracle on {sample} gates, {threads} "
-            "threads")
-        rate, wall, ok = cpu_baseline(p, bsk, ksk, wires_np, gates_np,
-                                      outs[main_form], sample, threads)
+        log(f"[bench] cpu baseline: oracle, {threads} threads, at least "
+            f"{args.cpu_sample} gates and {args.cpu_seconds:g} s")
+        rate, sample, wall, ok = cpu_baseline(
+            p, bsk, ksk, wires_np, gates_np, outs[main_form],
+            args.cpu_sample, args.cpu_seconds, threads)
         line["cpu_baseline"] = {
             "value": round(rate, 3), "unit": "bootstraps/s", "cores": threads,
             "kind": "oracle",

@@ -89,9 +89,10 @@ int cggi_params_check(const cggi_params_t *params);
 /* Create a context on the current HIP device.  Reads d_bsk
  * ([n][2l][2][N]) once to derive the key forms selected by `forms` (a
  * bitmask of cggi_form_t): the NTT form stores the bootstrapping key
- * transformed mod Q (8 * n*2l*2*N bytes), the INT8 form stores its limb
- * windows and a per-step offset correction.  d_bsk may be freed once this
- * call returns (it synchronises `stream`).  d_ksk ([N][t][2^gamma][n+1])
+ * transformed mod Q (8 * n*2l*2*N bytes), the INT8 form stores its int8
+ * limb windows (n*R*2*4*(N+64) bytes, R = 2l digit rows for Bg <= 2^7,
+ * 4l for Bg <= 2^13).  d_bsk may be freed once this call returns (it
+ * synchronises `stream`).  d_ksk ([N][t][2^gamma][n+1])
  * is NOT copied: it must stay valid and unchanged for the context's life.
  * `stream` is a hipStream_t (NULL = default stream).  On success *out
  * receives the context. */

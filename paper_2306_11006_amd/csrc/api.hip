@@ -115,7 +115,6 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
-    (void)hipFree(c->corr);
     (void)hipFree(c->ws_small);
     (void)hipFree(c->ws_big);
     (void)hipFree(c->ws_slot);

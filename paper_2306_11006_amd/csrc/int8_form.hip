@@ -21,26 +21,25 @@
 //    limbs v = sum_q 2^(8q) v_q; the four limb GEMMs accumulate in int32
 //    and are recombined mod 2^32.
 //  * Digits.  Gadget digits in [-Bg/2, Bg/2) are split into 7-bit
-//    sub-digits delta in [-64, 64) (one for Bg <= 2^7).  The operand holds
-//    delta + 64 in [0, 128) so that the sign flip of wrapped blocks stays in
-//    int8; the extra 64 * sum_r a_r * (1 + X + .. + X^(N-1)) is a per-step
-//    constant precomputed at context creation and entered, negated, as the
-//    starting value of the limb-0 accumulators.
-//  * Exactness: |sum| <= R*N*128*127 < 2^31, so int32 never overflows, and
+//    sub-digits delta in [-64, 64) (one for Bg <= 2^7); delta and its
+//    negation (for wrapped blocks) both fit int8.
+//  * Exactness: |sum| <= R*N*64*128 < 2^31, so int32 never overflows, and
 //    the recombination is a ring identity mod 2^32.
 //
 // Launch layout (N <= 1024): 512 threads (8 waves, two per SIMD) per
 // workgroup, one workgroup per CU (LDS-limited); a workgroup owns 4 column
-// tiles = 4*1024/N bootstraps.  Wave w computes output component
-// c' = w & 1 for the two column tiles 2((w>>1) % 2) and 2((w>>1) % 2) + 1
-// with four limb accumulators each (8 x 16 int32 registers), over the block
-// offsets Delta of parity w / 4; the two waves of a pair add their partial
-// sums into the LDS accumulator (mod 2^32, so the order does not matter).
+// tiles = 4*1024/N bootstraps.  Wave w computes output component c' = w & 1
+// and key limbs 2((w>>1) & 1), 2((w>>1) & 1) + 1 for all four tiles (8 x 16
+// int32 accumulators), over half w >> 2 of the block offsets Delta; the
+// four waves of one component add their partial sums into the LDS
+// accumulator (mod 2^32, so the order does not matter).  The A operand (key
+// window rows) is read from LDS once per Delta and reused by four MFMAs; the
+// B operand (digit blocks) of Delta + 1 is B of Delta shifted by one lane.
 // LDS holds the accumulators, the digit operands (both signs), the step's
 // key windows in four byte-shifted copies (so every lane reads its 16-byte
 // Toeplitz row as four aligned dwords), double-buffered per digit
 // polynomial, and the modulus-switched inputs.  N = 2048 runs 4 waves per
-// bootstrap with single-buffered windows (see I8Cfg).
+// bootstrap (all four limbs per wave) with single-buffered windows.
 #include "internal.hpp"
 
 namespace cggi {
@@ -50,12 +49,14 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int OFFSET = 64;      // digit operand bias
-
 // N <= 1024: a workgroup owns 4 column tiles (4 * 1024 / N bootstraps) and
-// runs 8 waves (two per SIMD) with double-buffered key windows.
+// runs 8 waves (two per SIMD) with double-buffered key windows; a wave
+// computes one output component and two of the four key limbs for all four
+// tiles over half of the block offsets (4 x 2 accumulators).
 // N = 2048: a bootstrap spans 2 column tiles; a workgroup owns one
-// bootstrap, runs 4 waves and single-buffers the (twice as long) windows.
+// bootstrap, runs 4 waves and single-buffers the (twice as long) windows; a
+// wave computes one output component and all four limbs for both tiles over
+// half of the block offsets (2 x 4 accumulators).
 template <int N> struct I8Cfg {
     static constexpr bool BIG = N > 1024;
     static constexpr int NB = N / 32;          // blocks per polynomial
@@ -64,6 +65,8 @@ template <int N> struct I8Cfg {
     static constexpr int TILES = BIG ? 2 : 4;       // column tiles per workgroup
     static constexpr int GPW = BIG ? TILES / TPG : TILES * GPT; // bootstraps
     static constexpr int THREADS = BIG ? 256 : 512;
+    static constexpr int LPW = BIG ? 4 : 2;    // key limbs per wave
+    static constexpr int WT = TILES;           // column tiles per wave
     static constexpr int EBUF = BIG ? 1 : 2;   // key-window buffers
     static constexpr int ELEN = N + 64;        // bytes per limb window
     static constexpr int EW = ELEN / 4;        // dwords per limb window
@@ -118,54 +121,6 @@ __global__ void k_int8_key(const uint32_t *__restrict__ bsk,
     }
 }
 
-// corr[i][c'][j] = 64 * (A * (1 + X + .. + X^(N-1)))[j] with
-// A = sum_r (sum_s 2^(7s)) a_{i,r,c'};  (A * 1)[j] = 2*prefix(j) - total.
-template <int N>
-__global__ __launch_bounds__(256) void k_int8_corr(
-    const uint32_t *__restrict__ bsk, uint32_t *__restrict__ corr, int l,
-    int S)
-{
-    __shared__ uint32_t A[N];
-    __shared__ uint32_t part[256];
-    const int i = blockIdx.x >> 1, cp = blockIdx.x & 1;
-    uint32_t w = 0;
-    for (int s = 0; s < S; ++s)
-        w += 1u << (7 * s);
-    for (int j = threadIdx.x; j < N; j += 256) {
-        uint32_t v = 0;
-        for (int r = 0; r < 2 * l; ++r)
-            v += bsk[(((size_t)i * 2 * l + r) * 2 + cp) * N + j];
-        A[j] = v * w;
-    }
-    __syncthreads();
-    // each thread scans a contiguous chunk, then the chunk totals
-    constexpr int CH = N / 256;
-    uint32_t run = 0;
-    for (int k = 0; k < CH; ++k) {
-        run += A[threadIdx.x * CH + k];
-        A[threadIdx.x * CH + k] = run;
-    }
-    part[threadIdx.x] = run;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (int k = 0; k < 256; ++k) {
-            uint32_t v = part[k];
-            part[k] = s;
-            s += v;
-        }
-    }
-    __syncthreads();
-    const uint32_t base = part[threadIdx.x];
-    for (int k = 0; k < CH; ++k)
-        A[threadIdx.x * CH + k] += base;
-    __syncthreads();
-    const uint32_t total = A[N - 1];
-    for (int j = threadIdx.x; j < N; j += 256)
-        corr[((size_t)i * 2 + cp) * N + j] =
-            (uint32_t)OFFSET * (2u * A[j] - total);
-}
-
 template <int N>
 struct I8Smem {
     using C = I8Cfg<N>;
@@ -181,7 +136,7 @@ struct I8Smem {
 // run time.
 template <int N, int L, int S>
 __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
-    const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
+    const int8_t *__restrict__ key,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
     int n, int beta, int l_rt, int S_rt)
@@ -285,22 +240,22 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
     __syncthreads();
 
     // ---- per-lane constants ----------------------------------------------
-    // waves w and w + TILES share a task and split the block offsets
-    // (even/odd); their partial sums meet in the fold
-    const int cp = wave & 1;                         // output component
-    const int ct0 = 2 * ((wave >> 1) % (TILES / 2)); // first of two tiles
-    const int half = wave / TILES;                   // block-offset parity
+    // waves that differ only in `half` split the block offsets; the
+    // partial sums of all waves of one output component meet in the fold
+    constexpr int WT = C::WT, LPW = C::LPW;
+    const int cp = wave & 1;                              // output component
+    const int q0 = BIG ? 0 : LPW * ((wave >> 1) & 1);     // first key limb
+    const int half = BIG ? wave >> 1 : wave >> 2;         // block-offset half
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
     // B operand: column c of tile t -> bootstrap in the workgroup and
     // output block J of that bootstrap
-    int glt[2], Jt[2];
+    int glt[WT], Jt[WT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int T = ct0 + t;
-        glt[t] = BIG ? T / TPG : T * GPT + rho / NB;
-        Jt[t] = BIG ? 32 * (T % TPG) + rho : rho % NB;
+    for (int T = 0; T < WT; ++T) {
+        glt[T] = BIG ? T / TPG : T * GPT + rho / NB;
+        Jt[T] = BIG ? 32 * (T % TPG) + rho : rho % NB;
     }
 
     const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
@@ -310,28 +265,9 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
     const uint32_t bmask = (1u << beta) - 1u;
     const int32_t bhalf = 1 << (beta - 1);
 
-    v16i Cacc[2][4];
+    v16i Cacc[WT][LPW];
 
     for (int i = 0; i < n; ++i) {
-        // The offset correction of this step enters as the starting value
-        // of the limb-0 accumulators (negated; int32 accumulation wraps mod
-        // 2^32, like the fold).  It is read here so the rotation phase hides
-        // the latency, and it is dead once the first MFMA group has run.
-        constexpr int NCI = BIG ? 2 : 1;   // tiles of one bootstrap differ
-        v16i c0init[NCI];
-#pragma unroll
-        for (int t = 0; t < NCI; ++t) {
-            const uint32_t *cr = corr + ((size_t)i * 2 + cp) * N + 32 * Jt[t] +
-                                 4 * hh;
-#pragma unroll
-            for (int a4 = 0; a4 < 4; ++a4) {
-                uint4 c4 = *reinterpret_cast<const uint4 *>(cr + 8 * a4);
-                c0init[t][4 * a4 + 0] = half ? 0 : -(int)c4.x;
-                c0init[t][4 * a4 + 1] = half ? 0 : -(int)c4.y;
-                c0init[t][4 * a4 + 2] = half ? 0 : -(int)c4.z;
-                c0init[t][4 * a4 + 3] = half ? 0 : -(int)c4.w;
-            }
-        }
         __syncthreads();   // ACC of the previous step complete
         // ---- rotate, subtract, decompose into digit operands --------------
         for (int item = tid; item < GPW * 2 * (N / 4); item += I8_THREADS) {
@@ -377,10 +313,13 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
                             sd = ((d[k] + 64) & 127) - 64;
                             d[k] = (d[k] - sd) >> 7;
                         }
-                        pos |= ((uint32_t)(sd + OFFSET) & 0xFFu) << (8 * (3 - k));
+                        pos |= ((uint32_t)sd & 0xFFu) << (8 * (3 - k));
                     }
-                    // bytes are in [0, 128): negate all four at once
-                    uint32_t neg = (0x80808080u - pos) ^ 0x80808080u;
+                    // negate the four bytes at once: ~b + 1 per byte, the
+                    // +1 kept inside each byte's low 7 bits
+                    const uint32_t npos = ~pos;
+                    uint32_t neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
+                                   (npos & 0x80808080u);
                     int kb = ((c * l) + (p - 1)) * SS + s;
                     int8_t *base = gbase + (size_t)kb * 2 * N;
                     *reinterpret_cast<uint32_t *>(base) = pos;
@@ -399,16 +338,17 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             const uint32_t *eb = ecop + (EBUF == 2 ? (st & 1) : 0) *
                                             (2 * 4 * 4 * CLEN) +
                                  cp * (4 * 4 * CLEN) + a_lane;
-            const int8_t *db[2];
+            const int8_t *db[WT];
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
+            for (int t = 0; t < WT; ++t)
                 db[t] = dig + ((size_t)(glt[t] * R + kb) * 2) * N +
                         hh * (NB * 16);
-            // A operand of block offset dl: 4 limb rows of the Toeplitz window
-            auto load_a = [&](int dl, v4i (&af)[4]) {
+            // A operand of block offset dl: this wave's limb rows of the
+            // Toeplitz window
+            auto load_a = [&](int dl, v4i (&af)[LPW]) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t *apq = eb + q * (4 * CLEN) + 8 * dl;
+                for (int q = 0; q < LPW; ++q) {
+                    const uint32_t *apq = eb + (q0 + q) * (4 * CLEN) + 8 * dl;
                     af[q][0] = (int)apq[0];
                     af[q][1] = (int)apq[1];
                     af[q][2] = (int)apq[2];
@@ -417,9 +357,9 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             };
             // B operand of block offset dl: the sign-rotated digit blocks of
             // both tiles
-            auto load_b = [&](int dl, v4i (&bf)[2]) {
+            auto load_b = [&](int dl, v4i (&bf)[WT]) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
+                for (int t = 0; t < WT; ++t) {
                     const int Mb = (Jt[t] - dl) & (NB - 1);
                     const int sg = Jt[t] < dl ? N : 0;
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
@@ -431,9 +371,9 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             // column of each run of output blocks, which reloads its block
             // (the one that wraps, negated) from LDS.
             constexpr int RUN = NB < 32 ? NB : 32;   // lanes per run of blocks
-            auto next_b = [&](int dl, v4i (&bf)[2]) {
+            auto next_b = [&](int dl, v4i (&bf)[WT]) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
+                for (int t = 0; t < WT; ++t)
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         bf[t][k] = __builtin_amdgcn_mov_dpp(bf[t][k], 0x138, 0xF,
@@ -445,29 +385,25 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
             // this wave's block offsets: dl0 .. dl0 + ND - 1
             const int dl0 = half * ND;
-            v4i bf[2];
+            v4i bf[WT];
             load_b(dl0, bf);
             {
-                v4i af[4];
+                v4i af[LPW];
                 load_a(dl0, af);
                 if (kb == 0) {
-                    // first group of the step: accumulators start from the
-                    // correction (limb 0) and zero (limbs 1..3)
+                    // first group of the step: accumulators start from zero
                     const v16i zero = {};
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        Cacc[t][0] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[0], bf[t], c0init[BIG ? t : 0], 0, 0, 0);
+                    for (int q = 0; q < LPW; ++q)
 #pragma unroll
-                        for (int q = 1; q < 4; ++q)
+                        for (int t = 0; t < WT; ++t)
                             Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                 af[q], bf[t], zero, 0, 0, 0);
-                    }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < LPW; ++q)
 #pragma unroll
-                        for (int t = 0; t < 2; ++t)
+                        for (int t = 0; t < WT; ++t)
                             Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                                 af[q], bf[t], Cacc[t][q], 0, 0, 0);
                 }
@@ -476,13 +412,13 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             }
 #pragma unroll 1
             for (int d0 = 1; d0 < ND; ++d0) {
-                v4i af[4];
+                v4i af[LPW];
                 load_a(dl0 + d0, af);
                 next_b(dl0 + d0, bf);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                for (int q = 0; q < LPW; ++q)
 #pragma unroll
-                    for (int t = 0; t < 2; ++t)
+                    for (int t = 0; t < WT; ++t)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
                             af[q], bf[t], Cacc[t][q], 0, 0, 0);
                 // spread the next stage's LDS copies between MFMA groups
@@ -504,19 +440,20 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
             }
         }
 
-        // ---- fold limbs, subtract the offset correction, add into ACC -----
+        // ---- fold limbs, add into ACC ---------------------------------------
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < WT; ++t) {
             uint32_t *a = acc + (glt[t] * 2 + cp) * AST + 33 * Jt[t];
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 int row = 8 * (v >> 2) + 4 * hh + (v & 3);
-                uint32_t x = (uint32_t)Cacc[t][0][v] +
-                             ((uint32_t)Cacc[t][1][v] << 8) +
-                             ((uint32_t)Cacc[t][2][v] << 16) +
-                             ((uint32_t)Cacc[t][3][v] << 24);
-                // both waves of the pair add (mod 2^32, order-free)
-                atomicAdd(&a[row], x);
+                uint32_t x = 0;
+#pragma unroll
+                for (int q = 0; q < LPW; ++q)
+                    x += (uint32_t)Cacc[t][q][v] << (8 * q);
+                // every wave of this component adds its limbs' part over its
+                // block offsets (mod 2^32, order-free)
+                atomicAdd(&a[row], x << (8 * q0));
             }
         }
     }
@@ -559,22 +496,14 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     using C = I8Cfg<N>;
     const Shape &sh = c->sh;
     size_t kbytes = (size_t)sh.n * sh.R * 2 * 4 * C::ELEN;
-    size_t cbytes = (size_t)sh.n * 2 * N * sizeof(uint32_t);
     if (hipMalloc(&c->bsk_i8, kbytes) != hipSuccess) {
         c->bsk_i8 = nullptr;
         return set_error(CGGI_E_NOMEM, "hipMalloc of the int8 key failed");
-    }
-    if (hipMalloc(&c->corr, cbytes) != hipSuccess) {
-        c->corr = nullptr;
-        return set_error(CGGI_E_NOMEM, "hipMalloc of the int8 correction failed");
     }
     size_t total = (size_t)sh.n * sh.R * 2 * C::ELEN;
     int blocks = (int)((total + 255) / 256);
     hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
                        c->bsk_i8, sh.n, sh.l, sh.S);
-    CGGI_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_int8_corr<N>, dim3(sh.n * 2), dim3(256), 0, s, bsk,
-                       c->corr, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
 }
@@ -607,7 +536,7 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     }
     int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8<N, L, S>), dim3(grid),
-                       dim3(C::THREADS), smem, s, c->bsk_i8, c->corr, in,
+                       dim3(C::THREADS), smem, s, c->bsk_i8, in,
                        testv, out, B, d_count, sh.n, sh.beta, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;

@@ -37,7 +37,6 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
-    uint32_t *corr = nullptr;     // [n][2][N] offset correction per step
     // eval_level workspace
     int32_t ws_gates = 0;
     uint32_t *ws_small = nullptr; // [2G][n+1] bootstrap inputs

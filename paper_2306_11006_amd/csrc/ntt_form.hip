@@ -40,6 +40,28 @@ unsigned bitrev(unsigned x, int bits)
 // loads the 2^NS elements one radix-2^NS block touches, runs the NS stages
 // in registers and stores them back, so each LDS round trip (and barrier)
 // covers three stages.
+// NS Cooley-Tukey stages on the 2^NS elements of one block held in
+// registers: the block starts in group i of stage s0 (m0 = 2^s0 groups).
+template <int NS>
+__device__ __forceinline__ void fwd_block(uint64_t (&v)[1 << NS], int m0, int i,
+                                          const uint64_t *__restrict__ tw)
+{
+    constexpr int K = 1 << NS;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+        const int d = 1 << (NS - 1 - u);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k & d)
+                continue;
+            const uint64_t S = tw[(m0 << u) + (i << u) + (k >> (NS - u))];
+            const uint64_t U = v[k], V = gl::mul(v[k + d], S);
+            v[k] = gl::add(U, V);
+            v[k + d] = gl::sub(U, V);
+        }
+    }
+}
+
 template <int N, int NS>
 __device__ __forceinline__ void fwd_pass(uint64_t *a, int P, int s0,
                                          const uint64_t *__restrict__ tw)
@@ -57,19 +79,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t *a, int P, int s0,
 #pragma unroll
         for (int k = 0; k < K; ++k)
             v[k] = x[k * stride];
-#pragma unroll
-        for (int u = 0; u < NS; ++u) {
-            const int d = 1 << (NS - 1 - u);
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k & d)
-                    continue;
-                const uint64_t S = tw[(m0 << u) + (i << u) + (k >> (NS - u))];
-                const uint64_t U = v[k], V = gl::mul(v[k + d], S);
-                v[k] = gl::add(U, V);
-                v[k + d] = gl::sub(U, V);
-            }
-        }
+        fwd_block<NS>(v, m0, i, tw);
 #pragma unroll
         for (int k = 0; k < K; ++k)
             x[k * stride] = v[k];
@@ -91,25 +101,45 @@ __device__ __forceinline__ void ntt_fwd(uint64_t *a, int P,
         fwd_pass<N, 1>(a, P, s, tw);
 }
 
-// In-place inverse (Gentleman-Sande, bit-reversed input, natural output,
-// twiddles twi[h + i] = psi^-bitrev(h + i)), without the final 1/N scaling;
-// NS stages per LDS round trip as in the forward transform.
-template <int N, int NS>
-__device__ __forceinline__ void inv_pass(uint64_t *a, int P, int u0,
-                                         const uint64_t *__restrict__ twi)
+// Forward stages 3 .. log2 N - 2 of P polynomials (stages 0..2 are fused
+// with the decomposition, the last one with the pointwise product).
+template <int N>
+__device__ __forceinline__ void ntt_fwd_middle(uint64_t *a, int P,
+                                               const uint64_t *__restrict__ tw)
+{
+    constexpr int LOGN = __builtin_ctz(N);
+    constexpr int END = LOGN - 1;
+    int s = 3;
+    for (; s + 3 <= END; s += 3)
+        fwd_pass<N, 3>(a, P, s, tw);
+    if (END - s == 2)
+        fwd_pass<N, 2>(a, P, s, tw);
+    else if (END - s == 1)
+        fwd_pass<N, 1>(a, P, s, tw);
+}
+
+// NS inverse (Gentleman-Sande) stages from stage u0 on the two product
+// polynomials (bit-reversed input, natural output, twiddles
+// twi[h + i] = psi^-bitrev(h + i)), in place, or, for the last pass, added
+// into the torus accumulator as the centred lift (the 1/N scaling is folded
+// into the transformed key).
+template <int N, int NS, bool TO_ACC>
+__device__ __forceinline__ void inv_pass(uint64_t *a, int u0,
+                                         const uint64_t *__restrict__ twi,
+                                         uint32_t *acc)
 {
     constexpr int K = 1 << NS;
     const int t0 = 1 << u0;                 // half-span at the first stage
     const int span = t0 * K;                // block of the pass
-    const int per_poly = N / K;
-    for (int idx = threadIdx.x; idx < P * per_poly; idx += NTT_THREADS) {
+    constexpr int per_poly = N / K;
+    for (int idx = threadIdx.x; idx < 2 * per_poly; idx += NTT_THREADS) {
         const int poly = idx / per_poly, r = idx - poly * per_poly;
         const int blk = r / t0, off = r - blk * t0;
-        uint64_t *x = a + poly * N + blk * span + off;
+        const int base = poly * N + blk * span + off;
         uint64_t v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            v[k] = x[k * t0];
+            v[k] = a[base + k * t0];
 #pragma unroll
         for (int w = 0; w < NS; ++w) {
             const int d = 1 << w;
@@ -125,30 +155,45 @@ __device__ __forceinline__ void inv_pass(uint64_t *a, int P, int u0,
             }
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            x[k * t0] = v[k];
+        for (int k = 0; k < K; ++k) {
+            if (TO_ACC)
+                acc[base + k * t0] += gl::lift32(v[k]);
+            else
+                a[base + k * t0] = v[k];
+        }
     }
     __syncthreads();
 }
 
+// Inverse stages 1 .. log2 N - 1 (stage 0 is fused with the pointwise
+// product); the last pass adds the result into the accumulator.
 template <int N>
-__device__ __forceinline__ void ntt_inv(uint64_t *a, int P,
-                                        const uint64_t *__restrict__ twi)
+__device__ __forceinline__ void ntt_inv_to_acc(uint64_t *a,
+                                               const uint64_t *__restrict__ twi,
+                                               uint32_t *acc)
 {
     constexpr int LOGN = __builtin_ctz(N);
-    int u = 0;
-    for (; u + 3 <= LOGN; u += 3)
-        inv_pass<N, 3>(a, P, u, twi);
-    if (LOGN - u == 2)
-        inv_pass<N, 2>(a, P, u, twi);
-    else if (LOGN - u == 1)
-        inv_pass<N, 1>(a, P, u, twi);
+    constexpr int NSTG = LOGN - 1;          // stages 1 .. LOGN - 1
+    constexpr int REM = NSTG % 3;
+    constexpr int FULL = NSTG / 3;
+    int u = 1;
+    for (int f = 0; f < FULL; ++f, u += 3) {
+        if (REM == 0 && f == FULL - 1)
+            inv_pass<N, 3, true>(a, u, twi, acc);
+        else
+            inv_pass<N, 3, false>(a, u, twi, acc);
+    }
+    if (REM == 2)
+        inv_pass<N, 2, true>(a, u, twi, acc);
+    else if (REM == 1)
+        inv_pass<N, 1, true>(a, u, twi, acc);
 }
 
+// bsk -> NTT form, times 1/N (the inverse transform then needs no scaling)
 template <int N>
 __global__ __launch_bounds__(NTT_THREADS) void k_bsk_to_ntt(
     const uint32_t *__restrict__ bsk, uint64_t *__restrict__ out,
-    const uint64_t *__restrict__ tw, int npoly)
+    const uint64_t *__restrict__ tw, uint64_t ninv, int npoly)
 {
     __shared__ uint64_t a[N];
     int poly = blockIdx.x;
@@ -159,7 +204,7 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bsk_to_ntt(
     __syncthreads();
     ntt_fwd<N>(a, 1, tw);
     for (int j = threadIdx.x; j < N; j += NTT_THREADS)
-        out[(size_t)poly * N + j] = a[j];
+        out[(size_t)poly * N + j] = gl::mul(a[j], ninv);
 }
 
 __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
@@ -171,7 +216,7 @@ __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
 template <int N>
 __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
     const uint64_t *__restrict__ bsk_ntt, const uint64_t *__restrict__ tw,
-    const uint64_t *__restrict__ twi, uint64_t ninv,
+    const uint64_t *__restrict__ twi,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
     int n, int beta, int l)
@@ -224,34 +269,66 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
         const int e = ms[i];
         if (e == 0)      // X^0 * ACC - ACC = 0 decomposes to all-zero digits
             continue;
-        // rotate, subtract, decompose
-        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS) {
-            int c = idx / N, m = idx - c * N;
-            int t = (m - e) & (2 * N - 1);
-            uint32_t rot = t < N ? acc[c * N + t] : 0u - acc[c * N + t - N];
-            uint32_t w = rot - acc[c * N + m] + dig_off;
+        // (1) rotate, subtract, decompose, and forward stages 0..2: a thread
+        // takes the 8 coefficients m = off + k N/8 of one component, forms
+        // X^e ACC - ACC there, and runs each digit polynomial's radix-8
+        // block in registers
+        for (int idx = threadIdx.x; idx < 2 * (N / 8); idx += NTT_THREADS) {
+            const int c = idx / (N / 8), off = idx - c * (N / 8);
+            const uint32_t *ac = acc + c * N;
+            uint32_t w[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int m = off + k * (N / 8);
+                const int t = (m - e) & (2 * N - 1);
+                const uint32_t rot = t < N ? ac[t] : 0u - ac[t - N];
+                w[k] = rot - ac[m] + dig_off;
+            }
             for (int p = 1; p <= l; ++p) {
-                int32_t d = (int32_t)((w >> (32 - p * beta)) & bmask) - bhalf;
-                dig[(size_t)(c * l + p - 1) * N + m] = gl::from_i32(d);
+                uint64_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    v[k] = gl::from_i32(
+                        (int32_t)((w[k] >> (32 - p * beta)) & bmask) - bhalf);
+                fwd_block<3>(v, 1, 0, tw);
+                uint64_t *x = dig + (size_t)(c * l + p - 1) * N + off;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    x[k * (N / 8)] = v[k];
             }
         }
         __syncthreads();
-        ntt_fwd<N>(dig, L2, tw);
-        // pointwise: res[c'][k] = sum_r dig[r][k] * bsk_ntt[i][r][c'][k]
+        // (2) forward stages 3 .. log2 N - 2
+        ntt_fwd_middle<N>(dig, L2, tw);
+        // (3) last forward stage (pairs 2j, 2j+1), pointwise product with
+        // the key row summed over the 2l digit polynomials, and the first
+        // inverse stage (the same pairs)
         const uint64_t *row = bsk_ntt + (size_t)i * L2 * 2 * N;
-        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS) {
-            int cp = idx / N, k = idx - cp * N;
-            uint64_t s = 0;
-            for (int r = 0; r < L2; ++r)
-                s = gl::add(s, gl::mul(dig[(size_t)r * N + k],
-                                       row[((size_t)r * 2 + cp) * N + k]));
-            res[cp * N + k] = s;
+        for (int j = threadIdx.x; j < N / 2; j += NTT_THREADS) {
+            const uint64_t S = tw[N / 2 + j];
+            uint64_t s0[2] = {0, 0}, s1[2] = {0, 0};
+            for (int r = 0; r < L2; ++r) {
+                const uint64_t U = dig[(size_t)r * N + 2 * j];
+                const uint64_t V = gl::mul(dig[(size_t)r * N + 2 * j + 1], S);
+                const uint64_t x0 = gl::add(U, V), x1 = gl::sub(U, V);
+#pragma unroll
+                for (int cp = 0; cp < 2; ++cp) {
+                    const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(
+                        row + ((size_t)r * 2 + cp) * N + 2 * j);
+                    s0[cp] = gl::add(s0[cp], gl::mul(x0, kk.x));
+                    s1[cp] = gl::add(s1[cp], gl::mul(x1, kk.y));
+                }
+            }
+            const uint64_t Si = twi[N / 2 + j];
+#pragma unroll
+            for (int cp = 0; cp < 2; ++cp) {
+                res[cp * N + 2 * j] = gl::add(s0[cp], s1[cp]);
+                res[cp * N + 2 * j + 1] = gl::mul(gl::sub(s0[cp], s1[cp]), Si);
+            }
         }
         __syncthreads();
-        ntt_inv<N>(res, 2, twi);
-        for (int idx = threadIdx.x; idx < 2 * N; idx += NTT_THREADS)
-            acc[idx] += gl::lift32(gl::mul(res[idx], ninv));
-        __syncthreads();
+        // (4) inverse stages 1 .. log2 N - 1, the last pass adding into ACC
+        ntt_inv_to_acc<N>(res, twi, acc);
     }
 
     // sample extraction of coefficient 0
@@ -307,22 +384,23 @@ int ntt_transform_bsk(Ctx *c, const uint32_t *bsk, hipStream_t s)
         c->bsk_ntt = nullptr;
         return set_error(CGGI_E_NOMEM, "hipMalloc of the NTT key failed");
     }
+    const uint64_t ninv = gl::pow_host((uint64_t)sh.N, gl::Q - 2);
     switch (sh.N) {
     case 256:
         hipLaunchKernelGGL(k_bsk_to_ntt<256>, dim3(npoly), dim3(NTT_THREADS),
-                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, ninv, npoly);
         break;
     case 512:
         hipLaunchKernelGGL(k_bsk_to_ntt<512>, dim3(npoly), dim3(NTT_THREADS),
-                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, ninv, npoly);
         break;
     case 1024:
         hipLaunchKernelGGL(k_bsk_to_ntt<1024>, dim3(npoly), dim3(NTT_THREADS),
-                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, ninv, npoly);
         break;
     case 2048:
         hipLaunchKernelGGL(k_bsk_to_ntt<2048>, dim3(npoly), dim3(NTT_THREADS),
-                           0, s, bsk, c->bsk_ntt, c->tw_fwd, npoly);
+                           0, s, bsk, c->bsk_ntt, c->tw_fwd, ninv, npoly);
         break;
     default:
         return set_error(CGGI_E_PARAM, "NTT form: unsupported N");
@@ -345,9 +423,8 @@ static int launch_bs_ntt(const Ctx *c, const uint32_t *in,
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_done = true;
     }
-    uint64_t ninv = gl::pow_host((uint64_t)N, gl::Q - 2);
     hipLaunchKernelGGL(k_bootstrap_ntt<N>, dim3(B), dim3(NTT_THREADS), smem,
-                       s, c->bsk_ntt, c->tw_fwd, c->tw_inv, ninv, in, testv,
+                       s, c->bsk_ntt, c->tw_fwd, c->tw_inv, in, testv,
                        out, B, d_count, sh.n, sh.beta, sh.l);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;

@@ -91,6 +91,16 @@ def test_create_rejects_bad_arguments_before_any_gpu_work():
                              ctypes.byref(h)) == cggi.E_PARAM
     assert b"bg_bit" in L.cggi_last_error()
     assert h.value is None
+    # int8 form at N=1024 with eight digit rows (Bg=2^13, l=2): the
+    # workgroup's digit operands no longer fit the 160 KB of LDS
+    pw = cggi.params_struct(dataclasses.replace(params.DEFAULT, bg_bit=13,
+                                                l=2))
+    assert L.cggi_params_check(ctypes.byref(pw)) == cggi.OK
+    assert L.cggi_ctx_create(ctypes.byref(pw), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), 2, None,
+                             ctypes.byref(h)) == cggi.E_PARAM
+    assert b"LDS" in L.cggi_last_error()
+    assert h.value is None
 
 
 def test_batch_calls_reject_null_context():

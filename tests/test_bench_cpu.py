@@ -54,3 +54,29 @@ def test_stored_traffic_follows_the_source(tmp_path, monkeypatch):
     assert bench.stored_traffic() is None
     if same is not None:   # the committed counters match the committed kernel
         assert same > 0
+
+
+def test_cpu_baseline_sample_rounds():
+    """The oracle sample grows in rounds of `threads` gates until both the
+    least gate count and the least wall time are met."""
+    import numpy as np
+    import oracle as O
+    from paper_2306_11006_amd import inputs
+    p = params.TOY
+    bsk, ksk = inputs.uniform_keys(p, 11)
+    G = 12
+    wires = inputs.uniform_lwe(p, 12, 2 * G)
+    gates = np.array([[0, 2 * g, 2 * g + 1, 0, 2 * G + g] for g in range(G)],
+                     dtype=np.int32)
+    want = np.stack([O.gate(p, 0, bsk, ksk, wires[2 * g], wires[2 * g + 1])
+                     for g in range(G)])
+    rate, n, wall, ok = bench.cpu_baseline(p, bsk, ksk, wires, gates, want,
+                                           5, 0.0, 2)
+    assert n == 6 and ok and rate > 0
+    bad = want.copy()
+    bad[1, 0] ^= 1
+    assert not bench.cpu_baseline(p, bsk, ksk, wires, gates, bad, 1, 0.0,
+                                  2)[3]
+    # the whole batch when the time bound is never met
+    assert bench.cpu_baseline(p, bsk, ksk, wires, gates, want, 1, 1e9,
+                              4)[1] == G
