@@ -225,6 +225,20 @@ def main():
                 "frac": round(achieved / PEAK_MULMOD_T, 4), "traffic": None,
                 "kernel": "k_bootstrap_ntt<1024>"}
 
+    if main_form == "int8":
+        # what the GPU sustains for this MFMA with random vs zero operand
+        # bits (power limit); the published peak assumes the top clock
+        ceil_rand = cggi.measure_int8_mfma(40000, True)
+        ceil_zero = cggi.measure_int8_mfma(40000, False)
+        log(f"[bench] bare int8 MFMA loop: {ceil_rand:.0f} TOP/s random "
+            f"operands, {ceil_zero:.0f} TOP/s zero operands")
+        roof["measured_ceiling"] = {
+            "random_operands": round(ceil_rand, 1),
+            "zero_operands": round(ceil_zero, 1), "unit": "TOP/s",
+            "frac_of_random": round(roof["achieved"] / ceil_rand, 4),
+            "how": "bare v_mfma_i32_32x32x32_i8 loop, one 8-wave workgroup "
+                   "per CU (cggi_measure_int8_mfma)"}
+
     line = {
         "metric": METRIC, "value": round(r["bootstraps_per_s"], 1),
         "unit": "bootstraps/s", "n_gpus": 1, "steps": args.steps,

@@ -178,6 +178,20 @@ int cggi_ctx_profile(cggi_ctx *ctx, int enable);
 int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
                           double *ks_ms, int32_t *ks_launches);
 
+/* Diagnostic: the int8 MFMA rate this GPU sustains.  Times a bare loop of
+ * v_mfma_i32_32x32x32_i8 (`iters` iterations of 8 independent MFMAs per
+ * wave, one workgroup of 8 waves per CU, the int8 form's launch shape) on
+ * random (random_operands != 0) or all-zero operand bits, and writes the
+ * rate in tera-operations per second (2 per multiply-add) to *tops.  With
+ * random operands the GPU lowers its clock to stay within its power limit,
+ * so this is the ceiling the int8 blind rotation can approach; the
+ * published dense int8 rate assumes the top clock.  Not a batch call: it
+ * allocates and frees 64 KB of device memory, runs on the default stream
+ * of the current device and waits for completion.  CGGI_E_PARAM for
+ * iters < 1 or tops NULL, CGGI_E_HIP on a runtime error. */
+int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
+                           double *tops);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);
 

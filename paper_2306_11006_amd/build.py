@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcggi.so")
 SOURCES = ["api.hip", "ntt_form.hip", "int8_form.hip", "keyswitch.hip",
-           "level.hip", "levelize.cpp"]
+           "level.hip", "levelize.cpp", "diag.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CGGI_OFFLOAD_ARCH", "gfx950")

@@ -27,7 +27,8 @@ OPCODES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "MUX": 4, "NOT": 5,
 EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
            "cggi_eval_level", "cggi_levelize", "cggi_ctx_profile",
-           "cggi_ctx_profile_read", "cggi_last_error"]
+           "cggi_ctx_profile_read", "cggi_measure_int8_mfma",
+           "cggi_last_error"]
 
 
 class CggiError(RuntimeError):
@@ -93,6 +94,15 @@ def params_check(p):
     ps = params_struct(p)
     rc = L.cggi_params_check(ctypes.byref(ps))
     return rc, (L.cggi_last_error().decode() if rc else "")
+
+
+def measure_int8_mfma(iters=40000, random_operands=True):
+    """Tera int8 operations per second a bare v_mfma_i32_32x32x32_i8 loop
+    sustains on the current device (random or all-zero operands)."""
+    out = ctypes.c_double()
+    _check(lib().cggi_measure_int8_mfma(int(iters), int(bool(random_operands)),
+                                        ctypes.byref(out)))
+    return out.value
 
 
 def levelize(gates, n_wires):

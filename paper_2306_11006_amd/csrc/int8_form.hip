@@ -33,8 +33,9 @@
 // int32 accumulators), over half w >> 2 of the block offsets Delta; the
 // four waves of one component add their partial sums into the LDS
 // accumulator (mod 2^32, so the order does not matter).  The A operand (key
-// window rows) is read from LDS once per Delta and reused by four MFMAs; the
-// B operand (digit blocks) of Delta + 1 is B of Delta shifted by one lane.
+// window rows) is read from LDS once per Delta and reused by four MFMAs, the
+// B operand (digit blocks of a tile) by two; the operands of Delta + 1 are
+// read in the issue shadows of Delta's MFMAs.
 // LDS holds the accumulators, the digit operands (both signs), the step's
 // key windows in four byte-shifted copies (so every lane reads its 16-byte
 // Toeplitz row as four aligned dwords), double-buffered per digit
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
 {
     using C = I8Cfg<N>;
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
-    constexpr int TILES = C::TILES, EBUF = C::EBUF;
+    constexpr int EBUF = C::EBUF;
     constexpr bool BIG = C::BIG;
     constexpr int I8_THREADS = C::THREADS;
     constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW, AST = C::AST;
@@ -365,66 +366,51 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
                 }
             };
-            // B of dl + 1 from B of dl: column J takes column J - 1's block
-            // with the same sign rule (J - 1 < dl iff J < dl + 1), so a
-            // one-lane shift (DPP wave_shr:1) gives every lane but the first
-            // column of each run of output blocks, which reloads its block
-            // (the one that wraps, negated) from LDS.
-            constexpr int RUN = NB < 32 ? NB : 32;   // lanes per run of blocks
-            auto next_b = [&](int dl, v4i (&bf)[WT]) {
+            constexpr int ND = NB / 2;    // block offsets per wave
+            constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
+            // this wave's block offsets: dl0 .. dl0 + ND - 1.  Group d0
+            // reads the operands of d0 + 1 into the other register buffer
+            // in the issue shadows of its own MFMAs (one LDS read and a few
+            // address ops after each MFMA).
+            const int dl0 = half * ND;
+            v4i af[2][LPW], bf[2][WT];
+            auto group = [&](int d0, int b, bool zero_start) {
+                if (d0 + 1 < ND) {
+                    load_a(dl0 + d0 + 1, af[b ^ 1]);
+                    load_b(dl0 + d0 + 1, bf[b ^ 1]);
+                }
+                const v16i zero = {};
 #pragma unroll
                 for (int t = 0; t < WT; ++t)
 #pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        bf[t][k] = __builtin_amdgcn_mov_dpp(bf[t][k], 0x138, 0xF,
-                                                            0xF, true);
-                if ((rho & (RUN - 1)) == 0)
-                    load_b(dl, bf);
-            };
-            constexpr int ND = NB / 2;    // block offsets per wave
-            constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
-            // this wave's block offsets: dl0 .. dl0 + ND - 1
-            const int dl0 = half * ND;
-            v4i bf[WT];
-            load_b(dl0, bf);
-            {
-                v4i af[LPW];
-                load_a(dl0, af);
-                if (kb == 0) {
-                    // first group of the step: accumulators start from zero
-                    const v16i zero = {};
-#pragma unroll
                     for (int q = 0; q < LPW; ++q)
-#pragma unroll
-                        for (int t = 0; t < WT; ++t)
-                            Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                af[q], bf[t], zero, 0, 0, 0);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < LPW; ++q)
-#pragma unroll
-                        for (int t = 0; t < WT; ++t)
-                            Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                af[q], bf[t], Cacc[t][q], 0, 0, 0);
-                }
-                if (EBUF == 2 && more && STASH0 == 0)
-                    stash_dyn((st + 1) & 1, 0);
-            }
-#pragma unroll 1
-            for (int d0 = 1; d0 < ND; ++d0) {
-                v4i af[LPW];
-                load_a(dl0 + d0, af);
-                next_b(dl0 + d0, bf);
-#pragma unroll
-                for (int q = 0; q < LPW; ++q)
-#pragma unroll
-                    for (int t = 0; t < WT; ++t)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[q], bf[t], Cacc[t][q], 0, 0, 0);
+                            af[b][q], bf[b][t], zero_start ? zero : Cacc[t][q],
+                            0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < WT * LPW; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0); // DS read
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0); // VALU
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 // spread the next stage's LDS copies between MFMA groups
                 if (EBUF == 2 && more && d0 >= STASH0 && d0 - STASH0 < PER_T)
                     stash_dyn((st + 1) & 1, d0 - STASH0);
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            load_a(dl0, af[0]);
+            load_b(dl0, bf[0]);
+            if (kb == 0)
+                group(0, 0, true);    // accumulators start from zero
+            else
+                group(0, 0, false);
+#pragma unroll 1
+            for (int d0 = 1; d0 + 1 < ND; d0 += 2) {
+                group(d0, 1, false);
+                group(d0 + 1, 0, false);
             }
+            group(ND - 1, 1, false);
             if (EBUF == 2 && ND < PER_T + 4 && more) {
                 // small N: fewer MFMA groups than copy items
                 for (int k = ND - STASH0; k < PER_T; ++k)

@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include",
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(cggi_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(cggi_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_function():
@@ -101,6 +101,14 @@ def test_create_rejects_bad_arguments_before_any_gpu_work():
                              ctypes.byref(h)) == cggi.E_PARAM
     assert b"LDS" in L.cggi_last_error()
     assert h.value is None
+
+
+def test_mfma_ceiling_rejects_bad_arguments():
+    import ctypes
+    L = cggi.lib()
+    out = ctypes.c_double()
+    assert L.cggi_measure_int8_mfma(0, 1, ctypes.byref(out)) == cggi.E_PARAM
+    assert L.cggi_measure_int8_mfma(10, 1, None) == cggi.E_PARAM
 
 
 def test_batch_calls_reject_null_context():
