@@ -135,3 +135,51 @@ def test_large_random_dag(O, large_uniform):
         want = list(ex.map(one, pick))
     for k, wv in zip(pick, want):
         assert np.array_equal(outs["int8"][int(lv[k][4])], wv), k
+
+
+def test_large_random_dag_wide(O, large_uniform):
+    """A 20,000-gate random DAG with log-uniform level widths up to 8192
+    (levels that span thousands of workgroups of the N=2048 kernels): the
+    two forms agree on every wire, and gates of the widest level (first,
+    last and six spread between) equal the oracle on that level's inputs."""
+    import time
+    import torch
+    from paper_2306_11006_amd import cggi
+    from paper_2306_11006_amd.circuit import LevelledCircuit
+    p, bsk, ksk, ctx = large_uniform
+    nl = inputs.random_dag(2060, 20000, max_width=8192)
+    circ = LevelledCircuit(nl.array(), nl.n_wires)
+    wires = np.zeros((nl.n_wires, p.n + 1), dtype=np.uint32)
+    wires[nl.input_wires] = inputs.uniform_lwe(p, 2061, len(nl.input_wires))
+    widest = int(np.argmax(circ.widths))
+    outs, before = {}, {}
+    ctx.reserve(max(circ.widths))
+    for form in FORMS:
+        say(f"large wide DAG ({circ.n_levels} levels, widest "
+            f"{max(circ.widths)}, {circ.bootstraps()} bootstraps) form={form}")
+        w = cggi.to_device(wires)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for L, lv in enumerate(circ.d_levels):
+            if L == widest:
+                torch.cuda.synchronize()
+                before[form] = cggi.to_host(w)
+            ctx.eval_level(form, lv, w)
+        torch.cuda.synchronize()
+        say(f"  {time.perf_counter() - t0:.2f} s")
+        outs[form] = cggi.to_host(w)
+    assert np.array_equal(outs["ntt"], outs["int8"])
+    assert np.array_equal(before["ntt"], before["int8"])
+    lv = circ.levels[widest]
+    pick = sorted({0, len(lv) - 1} |
+                  {int(k) for k in np.linspace(1, len(lv) - 2, 6)})
+    w0 = before["int8"]
+
+    def one(k):
+        op, a, b, c, _ = (int(v) for v in lv[k])
+        return O.gate(p, op, bsk, ksk, w0[a], w0[b], w0[c])
+
+    with cf.ThreadPoolExecutor(THREADS) as ex:
+        want = list(ex.map(one, pick))
+    for k, wv in zip(pick, want):
+        assert np.array_equal(outs["int8"][int(lv[k][4])], wv), k
