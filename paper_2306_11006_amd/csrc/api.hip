@@ -115,6 +115,7 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
+    (void)hipFree(c->ksk_i8);
     (void)hipFree(c->ws_small);
     (void)hipFree(c->ws_big);
     (void)hipFree(c->ws_slot);
@@ -235,6 +236,10 @@ int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
             free_ctx(c);
             return rc;
         }
+    }
+    if ((rc = keyswitch_make_key(c, s))) {
+        free_ctx(c);
+        return rc;
     }
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

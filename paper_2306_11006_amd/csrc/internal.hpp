@@ -37,6 +37,9 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
+    // key switch as an int8 GEMM (bases up to 2^4)
+    int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
+    int ks_ksj = 0;               // 32-slot K-steps per j
     // eval_level workspace
     int32_t ws_gates = 0;
     uint32_t *ws_small = nullptr; // [2G][n+1] bootstrap inputs
@@ -81,6 +84,7 @@ int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
 
 // Key switch.  in_a/in_b: optional second input added before switching
 // (MUX combine); the plain batch call passes null maps.
+int keyswitch_make_key(Ctx *c, hipStream_t s);
 int keyswitch_launch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
                      hipStream_t s);
 

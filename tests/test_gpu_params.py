@@ -1,6 +1,7 @@
 """Parameter sets beyond the three named ones: ring degree 512, digit widths
 that take the int8 form's generic (run-time l, S) kernel and its 7-bit
-sub-digit split, and key-switch bases from 2^1 to 2^4.  Both forms and the
+sub-digit split, and key-switch bases from 2^1 to 2^4 (int8 GEMM key
+switch) and 2^5 (row-gather key switch).  Both forms and the
 key switch are compared with the oracle coefficient by coefficient on
 uniform keys, for one full workgroup of bootstraps plus a ragged tail."""
 import concurrent.futures as cf
@@ -33,6 +34,11 @@ SETS = [
     # N=256, Bg=2^5 l=5: ten digit rows per CMux step, generic kernel
     params.Params("n256_bg5_l5", n=48, N=256, k=1, bg_bit=5, l=5,
                   ks_base_bit=2, ks_t=7, lwe_noise_log2=15,
+                  bk_noise_log2=25),
+    # key-switch base 2^5: past the int8 GEMM's one-hot width, so the key
+    # switch gathers key rows instead
+    params.Params("n256_ks32", n=64, N=256, k=1, bg_bit=8, l=2,
+                  ks_base_bit=5, ks_t=6, lwe_noise_log2=15,
                   bk_noise_log2=25),
 ]
 
