@@ -91,9 +91,12 @@ int cggi_params_check(const cggi_params_t *params);
  * bitmask of cggi_form_t): the NTT form stores the bootstrapping key
  * transformed mod Q (8 * n*2l*2*N bytes), the INT8 form stores its int8
  * limb windows (n*R*2*4*(N+64) bytes, R = 2l digit rows for Bg <= 2^7,
- * 4l for Bg <= 2^13).  d_bsk may be freed once this call returns (it
- * synchronises `stream`).  d_ksk ([N][t][2^gamma][n+1])
- * is NOT copied: it must stay valid and unchanged for the context's life.
+ * 4l for Bg <= 2^13).  For key-switch bases up to 2^4 the context also
+ * stores d_ksk as int8 limb blocks for the GEMM key switch
+ * (ceil((n+1)/32) * N * ceil(t*2^gamma/32) * 4 KB).  d_bsk may be freed
+ * once this call returns (it synchronises `stream`).  d_ksk
+ * ([N][t][2^gamma][n+1]) must stay valid and unchanged for the context's
+ * life (larger bases gather its rows directly).
  * `stream` is a hipStream_t (NULL = default stream).  On success *out
  * receives the context. */
 int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
@@ -125,8 +128,11 @@ int cggi_bootstrap_batch(cggi_ctx *ctx, cggi_form_t form,
 /* Key switch a batch (Fig. 1, last step): d_in[B][N+1] (key K) ->
  * d_out[B][n+1] (key s), out = (0,..,0, b') - sum_{j<N, p<t}
  * ksk[j][p][digit_p(a'_j)], with unsigned base-2^gamma digits of a'_j
- * rounded to t*gamma bits.  B == 0 is a no-op.  d_out must not overlap
- * d_in. */
+ * rounded to t*gamma bits.  Bases up to 2^4 run as an int8 GEMM of the
+ * one-hot digit matrix with the key, split over j and summed into d_out
+ * with device atomics (exact mod 2^32, so the result does not depend on
+ * their order); larger bases gather key rows.  B == 0 is a no-op.  d_out
+ * must not overlap d_in. */
 int cggi_keyswitch_batch(cggi_ctx *ctx, const uint32_t *d_in,
                          uint32_t *d_out, int32_t B, void *stream);
 
