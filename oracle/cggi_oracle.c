@@ -27,10 +27,10 @@
  *   - sample extraction takes coefficient 0.
  *
  * Parity status (see the tests): every function here is pinned by a closed
- * form, an exhaustive or brute-force check, or a decryption truth table,
- * except the key and noise generation helpers, whose only pin is
- * determinism per seed ("parity unpinned" for the Gaussian shape, which
- * lives in the input generator anyway).
+ * form, an exhaustive or brute-force check, or a decryption truth table.
+ * The key and noise generation helpers take their random draws as inputs;
+ * the rounded-Gaussian draws themselves come from the shared input
+ * generator and are pinned there by statistical tests.
  */
 #include <stdint.h>
 #include <stdlib.h>

@@ -82,3 +82,29 @@ def test_pin_catches_planted_mistake(name, tmp_path, monkeypatch):
         monkeypatch.setattr(api, "LIB", real)
         api.lib()
     assert isinstance(api._lib, ctypes.CDLL)
+
+
+def _noise(scale_shift=0, rounding=True, uniform=False):
+    import numpy as np
+
+    def f(g, shape, x):
+        if x is None:
+            return np.zeros(shape, dtype=np.int32)
+        z = (g.random(size=shape) - 0.5) * np.sqrt(12.0) if uniform \
+            else g.standard_normal(size=shape)
+        v = z * float(2 ** (32 - x - scale_shift))
+        v = np.rint(v) if rounding else v
+        return v.astype(np.int64).astype(np.int32)
+    return f
+
+
+@pytest.mark.parametrize("name,mutant", [
+    ("noise scale halved", _noise(scale_shift=1)),
+    ("noise truncated, not rounded", _noise(rounding=False)),
+    ("noise uniform, not Gaussian", _noise(uniform=True)),
+])
+def test_noise_pin_catches_planted_mistake(name, mutant, monkeypatch):
+    from paper_2306_11006_amd import inputs
+    monkeypatch.setattr(inputs, "gaussian_i32", mutant)
+    with pytest.raises(AssertionError):
+        pins.test_noise_draws_are_rounded_gaussians()

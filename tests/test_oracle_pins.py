@@ -391,6 +391,34 @@ def test_input_generators_deterministic():
     assert not np.array_equal(a["bsk_a"], c["bsk_a"])
 
 
+def test_noise_draws_are_rounded_gaussians():
+    """The noise generator against the distribution it claims: 400k draws
+    of round(2^(32-x) z), z ~ N(0, 1), at x = 15 (the default LWE noise)
+    have mean ~ 0 and standard deviation 2^17 within 0.5% (the sampling
+    error is about 0.1%), pass a Kolmogorov-Smirnov test against N(0, 2^34),
+    are integers, and put 68.3% / 95.4% within 1 / 2 sigma.  A wrong scale
+    (2^(31-x)), a missing rounding or a uniform draw fails one of these."""
+    from scipy import stats
+    g = inputs.rng(4242)
+    sigma = 2.0 ** (32 - 15)
+    e = inputs.gaussian_i32(g, 400_000, 15).astype(np.float64)
+    assert abs(e.mean()) < 4 * sigma / np.sqrt(len(e))
+    assert abs(e.std() / sigma - 1.0) < 5e-3
+    assert stats.kstest(e / sigma, "norm").pvalue > 1e-3
+    for k, frac in ((1, 0.6827), (2, 0.9545)):
+        assert abs(np.mean(np.abs(e) <= k * sigma) - frac) < 5e-3
+    # rounding to the nearest integer: at x = 30 the std is 4, so the draws
+    # are small integers whose histogram matches the rounded normal
+    small = inputs.gaussian_i32(inputs.rng(4243), 400_000, 30)
+    assert small.dtype == np.int32
+    vals, counts = np.unique(small, return_counts=True)
+    want = (stats.norm.cdf((vals + 0.5) / 4.0) -
+            stats.norm.cdf((vals - 0.5) / 4.0)) * len(small)
+    big = want > 50
+    chi2 = float((((counts - want) ** 2) / want)[big].sum())
+    assert chi2 < stats.chi2.ppf(0.999, int(big.sum()) - 1)
+
+
 def test_golden_ntt_params():
     """The paper's NTT modulus and generator (tests/golden/ntt_params.txt):
     Q = 2^64 - 2^32 + 1 is prime-field modulus of the exact products and g
