@@ -225,6 +225,11 @@ def main():
                 "frac": round(achieved / PEAK_MULMOD_T, 4), "traffic": None,
                 "kernel": "k_bootstrap_ntt<1024>"}
 
+    if main_form == "int8" and roof.get("traffic"):
+        # the HBM side of the same launch: measured bytes over its duration
+        gbs = roof["traffic"] / (r["bs_kernel_ms"] * 1e-3) / 1e9
+        roof["traffic_gb_per_s"] = round(gbs, 1)
+        roof["traffic_frac_of_hbm"] = round(gbs / 8000.0, 5)
     if main_form == "int8":
         # what the GPU sustains for this MFMA with random vs zero operand
         # bits (power limit); the published peak assumes the top clock
