@@ -221,9 +221,11 @@ int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
     c->sh = sh;
     c->forms = forms;
     c->ksk = d_ksk;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount,
+                              c->device) != hipSuccess || c->cus < 1) {
         free_ctx(c);
-        return set_error(CGGI_E_HIP, "hipGetDevice failed");
+        return set_error(CGGI_E_HIP, "hipGetDevice / CU count failed");
     }
     if (forms & CGGI_FORM_NTT) {
         if ((rc = ntt_make_tables(c, s)) || (rc = ntt_transform_bsk(c, d_bsk, s))) {

@@ -58,12 +58,15 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // bootstrap, runs 4 waves and single-buffers the (twice as long) windows; a
 // wave computes one output component and all four limbs for both tiles over
 // half of the block offsets (2 x 4 accumulators).
-template <int N> struct I8Cfg {
+// T (N <= 1024) is the number of column tiles per workgroup: 4 for wide
+// batches; 2 or 1 for narrow ones, so that a batch of few bootstraps spreads
+// over more CUs and each workgroup's step does less work.
+template <int N, int T = 4> struct I8Cfg {
     static constexpr bool BIG = N > 1024;
     static constexpr int NB = N / 32;          // blocks per polynomial
     static constexpr int TPG = BIG ? N / 1024 : 1;  // column tiles per bootstrap
     static constexpr int GPT = BIG ? 1 : 1024 / N;  // bootstraps per column tile
-    static constexpr int TILES = BIG ? 2 : 4;       // column tiles per workgroup
+    static constexpr int TILES = BIG ? 2 : T;       // column tiles per workgroup
     static constexpr int GPW = BIG ? TILES / TPG : TILES * GPT; // bootstraps
     static constexpr int THREADS = BIG ? 256 : 512;
     static constexpr int LPW = BIG ? 4 : 2;    // key limbs per wave
@@ -122,9 +125,9 @@ __global__ void k_int8_key(const uint32_t *__restrict__ bsk,
     }
 }
 
-template <int N>
+template <int N, int T = 4>
 struct I8Smem {
-    using C = I8Cfg<N>;
+    using C = I8Cfg<N, T>;
     static constexpr size_t ecop = (size_t)C::ECOP_DW * 4;
     static constexpr size_t acc = (size_t)C::GPW * 2 * C::AST * 4;
     static size_t dig(int R) { return (size_t)C::GPW * R * 2 * N; }
@@ -135,14 +138,14 @@ struct I8Smem {
 // L (gadget levels) and S (sub-digits per digit) are compile-time so the
 // digit loops unroll; L = 0 selects a generic build that reads l and S at
 // run time.
-template <int N, int L, int S>
-__global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
+template <int N, int L, int S, int T>
+__global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     const int8_t *__restrict__ key,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
     int n, int beta, int l_rt, int S_rt)
 {
-    using C = I8Cfg<N>;
+    using C = I8Cfg<N, T>;
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
     constexpr int EBUF = C::EBUF;
     constexpr bool BIG = C::BIG;
@@ -254,9 +257,9 @@ __global__ __launch_bounds__(I8Cfg<N>::THREADS, 1) void k_bootstrap_int8(
     // output block J of that bootstrap
     int glt[WT], Jt[WT];
 #pragma unroll
-    for (int T = 0; T < WT; ++T) {
-        glt[T] = BIG ? T / TPG : T * GPT + rho / NB;
-        Jt[T] = BIG ? 32 * (T % TPG) + rho : rho % NB;
+    for (int tt = 0; tt < WT; ++tt) {
+        glt[tt] = BIG ? tt / TPG : tt * GPT + rho / NB;
+        Jt[tt] = BIG ? 32 * (tt % TPG) + rho : rho % NB;
     }
 
     const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
@@ -505,27 +508,46 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
     }
 }
 
-template <int N, int L, int S>
+template <int N, int L, int S, int T>
 static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
                             const uint32_t *testv, uint32_t *out, int B,
                             const int32_t *d_count, hipStream_t s)
 {
-    using C = I8Cfg<N>;
+    using C = I8Cfg<N, T>;
     const Shape &sh = c->sh;
-    size_t smem = I8Smem<N>::total(sh.R, sh.n);
+    size_t smem = I8Smem<N, T>::total(sh.R, sh.n);
     static bool attr_done = false;
     if (!attr_done) {
         CGGI_HIP_TRY(hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S>),
+            reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S, T>),
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_done = true;
     }
     int grid = (B + C::GPW - 1) / C::GPW;
-    hipLaunchKernelGGL((k_bootstrap_int8<N, L, S>), dim3(grid),
+    hipLaunchKernelGGL((k_bootstrap_int8<N, L, S, T>), dim3(grid),
                        dim3(C::THREADS), smem, s, c->bsk_i8, in,
                        testv, out, B, d_count, sh.n, sh.beta, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
+}
+
+// Column tiles per workgroup for a batch of (at most) B bootstraps: the
+// fewest that still fit the batch into one wave of workgroups over the CUs.
+template <int N, int L, int S>
+static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
+                            const uint32_t *testv, uint32_t *out, int B,
+                            const int32_t *d_count, hipStream_t s)
+{
+    if constexpr (N <= 1024) {
+        const long tiles = (B + I8Cfg<N>::GPT - 1) / I8Cfg<N>::GPT;
+        if (tiles <= c->cus)
+            return launch_bs_int8_t<N, L, S, 1>(c, in, testv, out, B, d_count,
+                                                s);
+        if (tiles <= 2L * c->cus)
+            return launch_bs_int8_t<N, L, S, 2>(c, in, testv, out, B, d_count,
+                                                s);
+    }
+    return launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, B, d_count, s);
 }
 
 template <int N>
@@ -536,10 +558,10 @@ static int launch_bs_int8(const Ctx *c, const uint32_t *in,
     const Shape &sh = c->sh;
     // specialised digit loops for the parameter sets in use, generic else
     if (sh.l == 3 && sh.S == 1)
-        return launch_bs_int8_t<N, 3, 1>(c, in, testv, out, B, d_count, s);
+        return launch_bs_int8_w<N, 3, 1>(c, in, testv, out, B, d_count, s);
     if (sh.l == 2 && sh.S == 2)
-        return launch_bs_int8_t<N, 2, 2>(c, in, testv, out, B, d_count, s);
-    return launch_bs_int8_t<N, 0, 0>(c, in, testv, out, B, d_count, s);
+        return launch_bs_int8_w<N, 2, 2>(c, in, testv, out, B, d_count, s);
+    return launch_bs_int8_w<N, 0, 0>(c, in, testv, out, B, d_count, s);
 }
 
 int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,

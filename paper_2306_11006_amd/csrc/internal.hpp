@@ -29,6 +29,7 @@ struct cggi_ctx {
     cggi_params_t p;
     cggi::Shape sh;
     int device;
+    int cus = 256;                // compute units of the device
     uint32_t forms;
     const uint32_t *ksk;          // caller-owned [N][t][2^gamma][n+1]
     // NTT form

@@ -186,6 +186,24 @@ def test_default_ragged_small_batch(O, default_uniform):
         assert np.array_equal(gpu_bootstrap(ctx, form, cts), want), form
 
 
+@pytest.mark.parametrize("B", [200, 400, 700])
+def test_default_batch_widths_pick_tiles(O, default_uniform, B):
+    """Batch widths that give the int8 form 1, 2 and 4 column tiles per
+    workgroup (at most one wave of workgroups over the CUs): the forms agree
+    on every output and the first and last bootstraps equal the oracle."""
+    p, bsk, ksk, ctx = default_uniform
+    cts = inputs.uniform_lwe(p, 3400 + B, B)
+    outs = {}
+    for form in FORMS:
+        say(f"default bootstrap form={form} B={B}")
+        outs[form] = gpu_bootstrap(ctx, form, cts)
+    assert np.array_equal(outs["ntt"], outs["int8"])
+    idx = [0, B - 1]
+    want = oracle_map(lambda i: O.bootstrap(p, bsk, cts[i]), idx)
+    for i, w in zip(idx, want):
+        assert np.array_equal(outs["int8"][i], w), i
+
+
 def test_default_keyswitch_bit_exact(O, default_uniform):
     p, bsk, ksk, ctx = default_uniform
     cts = inputs.uniform_lwe(p, 5170, 67, dim=p.N)
