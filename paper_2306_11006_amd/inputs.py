@@ -188,7 +188,7 @@ def array_multiplier(nl, a, b):
         acc = new[1:]
         carry_top = c
     out += acc
-    out.append(carry_top)
+    out.append(nl.gate("CONST0") if carry_top is None else carry_top)
     return out
 
 
