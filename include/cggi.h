@@ -63,8 +63,10 @@ enum {
     CGGI_E_ALIAS = -3,       /* output overlaps an input                    */
     CGGI_E_HIP = -4,         /* a HIP runtime call failed                   */
     CGGI_E_NOMEM = -5,       /* device allocation failed                    */
-    CGGI_E_UNSUPPORTED = -6  /* form not built into the context, or an
+    CGGI_E_UNSUPPORTED = -6, /* form not built into the context, or an
                                 allocation would be needed during capture   */
+    CGGI_E_TIMEOUT = -7      /* a latency-mode bootstrap's workgroups did
+                                not meet (see cggi_ctx_check)               */
 };
 
 /* Gate opcodes of cggi_eval_level.  MUX(in0 = select, in1 = value if 1,
@@ -197,6 +199,30 @@ int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
  * iters < 1 or tops NULL, CGGI_E_HIP on a runtime error. */
 int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
                            double *tops);
+
+/* Latency mode of the INT8 form (N <= 1024).  ArctyrEX's closing section
+ * names splitting one gate over several SMs as the way to speed up narrow
+ * circuit levels; here a narrow batch runs each column tile's blind
+ * rotation (1024/N bootstraps) on four workgroups on four CUs, one per
+ * (output component, pair of key limbs), which exchange their partial
+ * products after every CMux step through device memory.  Results are
+ * bit-identical to the one-workgroup kernel.  A cggi_bootstrap_batch or
+ * cggi_eval_level call of the INT8 form uses it when it is on and the
+ * call's B (2G for a level of G gates) needs at most *groups tiles, where
+ * cggi_ctx_latency_groups reports the context's limit (every workgroup of
+ * such a launch is resident at once; 0 when latency mode is off or
+ * unavailable: N = 2048, more than 12 digit polynomials, or LDS).  It is on
+ * by default; cggi_ctx_latency_mode(ctx, 0) turns it off, e.g. when other
+ * streams keep the GPU's CUs busy, since the four workgroups of a tile wait
+ * for each other.  Each wait is bounded (1 s): on a time-out the kernel
+ * sets an error word in the context and stops, and every later latency-mode
+ * launch on the context does nothing until cggi_ctx_check, which waits for
+ * the device, returns CGGI_E_TIMEOUT if the word was set (clearing it and
+ * the exchange buffers), else CGGI_OK.  Latency-mode launches on one
+ * context must not run concurrently (they share its exchange buffers). */
+int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable);
+int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups);
+int cggi_ctx_check(cggi_ctx *ctx);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);

@@ -18,8 +18,8 @@ FORM_INT8 = 2
 FORMS = {"ntt": FORM_NTT, "int8": FORM_INT8}
 
 OK = 0
-E_PARAM, E_SHAPE, E_ALIAS, E_HIP, E_NOMEM, E_UNSUPPORTED = -1, -2, -3, -4, \
-    -5, -6
+E_PARAM, E_SHAPE, E_ALIAS, E_HIP, E_NOMEM, E_UNSUPPORTED, E_TIMEOUT = \
+    -1, -2, -3, -4, -5, -6, -7
 
 OPCODES = {"NAND": 0, "AND": 1, "OR": 2, "XOR": 3, "MUX": 4, "NOT": 5,
            "COPY": 6, "CONST0": 7, "CONST1": 8, "NOR": 9, "XNOR": 10}
@@ -28,7 +28,8 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
            "cggi_eval_level", "cggi_levelize", "cggi_ctx_profile",
            "cggi_ctx_profile_read", "cggi_measure_int8_mfma",
-           "cggi_last_error"]
+           "cggi_ctx_latency_mode", "cggi_ctx_latency_groups",
+           "cggi_ctx_check", "cggi_last_error"]
 
 
 class CggiError(RuntimeError):
@@ -70,6 +71,9 @@ def lib():
         L.cggi_ctx_profile.argtypes = [vp, ctypes.c_int]
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)
         L.cggi_ctx_profile_read.argtypes = [vp, dp, ip, dp, ip]
+        L.cggi_ctx_latency_mode.argtypes = [vp, i32]
+        L.cggi_ctx_latency_groups.argtypes = [vp, ip]
+        L.cggi_ctx_check.argtypes = [vp]
         L.cggi_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -192,6 +196,22 @@ class Context:
                                            ctypes.byref(bn), ctypes.byref(km),
                                            ctypes.byref(kn)))
         return bm.value, bn.value, km.value, kn.value
+
+    def latency_mode(self, enable=True):
+        """Turn the INT8 form's latency mode (narrow batches over four CUs
+        per column tile) on or off."""
+        _check(lib().cggi_ctx_latency_mode(self._h, int(bool(enable))))
+
+    def latency_groups(self):
+        """Most column tiles a latency-mode launch takes (0: off)."""
+        g = ctypes.c_int32()
+        _check(lib().cggi_ctx_latency_groups(self._h, ctypes.byref(g)))
+        return g.value
+
+    def check(self):
+        """Wait for the device; raise CggiError(E_TIMEOUT) if a
+        latency-mode launch timed out since the last check."""
+        _check(lib().cggi_ctx_check(self._h))
 
     def reserve(self, max_gates):
         _check(lib().cggi_ctx_reserve(self._h, int(max_gates)))

@@ -115,6 +115,9 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
+    (void)hipFree(c->x_buf);
+    (void)hipFree(c->x_epoch);
+    (void)hipFree(c->x_err);
     (void)hipFree(c->ksk_i8);
     (void)hipFree(c->ws_small);
     (void)hipFree(c->ws_big);
@@ -392,6 +395,44 @@ int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
     if (ks_launches)
         *ks_launches = cnt[1];
     return CGGI_OK;
+}
+
+int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    ctx->split_on = enable != 0;
+    return CGGI_OK;
+}
+
+int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups)
+{
+    if (!ctx || !groups)
+        return set_error(CGGI_E_PARAM, "ctx or groups is NULL");
+    *groups = ctx->split_on ? ctx->split_groups : 0;
+    return CGGI_OK;
+}
+
+int cggi_ctx_check(cggi_ctx *ctx)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    CGGI_HIP_TRY(hipDeviceSynchronize());
+    if (!ctx->x_err)
+        return CGGI_OK;
+    uint32_t flag = 0;
+    CGGI_HIP_TRY(hipMemcpy(&flag, ctx->x_err, 4, hipMemcpyDeviceToHost));
+    if (!flag)
+        return CGGI_OK;
+    if ((rc = int8_split_reset(ctx)))
+        return rc;
+    return set_error(CGGI_E_TIMEOUT,
+                     "a latency-mode bootstrap timed out waiting for its "
+                     "workgroups; its outputs and those of later latency-mode "
+                     "calls since the last check are invalid");
 }
 
 const char *cggi_last_error(void)

@@ -72,6 +72,10 @@ template <int N, int T = 4> struct I8Cfg {
     static constexpr int LPW = BIG ? 4 : 2;    // key limbs per wave
     static constexpr int WT = TILES;           // column tiles per wave
     static constexpr int EBUF = BIG ? 1 : 2;   // key-window buffers
+    // stages between a key window's global read and its use: with one or
+    // two tiles a stage's MFMA work is too short to cover the read latency
+    // of the next window, so the read is issued two stages ahead
+    static constexpr int PD = (!BIG && T <= 2) ? 2 : 1;
     static constexpr int ELEN = N + 64;        // bytes per limb window
     static constexpr int EW = ELEN / 4;        // dwords per limb window
     static constexpr int CW = N / 4 + 8;       // dwords of a shifted copy used
@@ -134,6 +138,79 @@ struct I8Smem {
     static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
     static size_t total(int R, int n) { return ecop + acc + dig(R) + ms(n); }
 };
+
+// Rotate the accumulator of every bootstrap of the workgroup by
+// a~_i = ms[i] (X^(a~_i) ACC - ACC), add the digit offset and split each
+// coefficient into R signed int8 digit operands, in both signs (ArctyrEX
+// Fig. 1, the decomposition of the CMux step; Section 2.2).
+// Layout of dig: [GPW][R][2 signs][N] bytes; within a polynomial the 16
+// bytes of each lane's B operand hold one 32-block's kappa in reverse.
+template <int N, int L, int S, int GPW, int THREADS>
+__device__ __forceinline__ void decompose_acc(
+    const uint32_t *acc, int8_t *dig, const uint16_t *ms, int i, int n, int l,
+    int SS, int R, int beta, uint32_t dig_off, uint32_t bmask, int32_t bhalf,
+    int tid)
+{
+    constexpr int NB = N / 32, AST = N + N / 32;
+    auto ap = [](int j) { return j + (j >> 5); };
+    for (int item = tid; item < GPW * 2 * (N / 4); item += THREADS) {
+        int gl = item / (2 * (N / 4));
+        int rem = item - gl * (2 * (N / 4));
+        int c = rem / (N / 4);
+        int m0 = 4 * (rem - c * (N / 4));
+        int e = ms[gl * (n + 1) + i];
+        const uint32_t *a = acc + (gl * 2 + c) * AST;
+        const int pm0 = ap(m0);           // the quad stays in one block
+        uint32_t w4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int t = (m0 + k - e) & (2 * N - 1);
+            uint32_t rv = a[ap(t & (N - 1))];
+            rv = t >= N ? 0u - rv : rv;
+            w4[k] = rv - a[pm0 + k] + dig_off;
+        }
+        // byte b of the dword holds coefficient m0 + 3 - b (reversed kappa)
+        int kap0 = m0 & 31, M = m0 >> 5;
+        int kp = 28 - kap0;                 // kappa' of byte 0
+        int off = (kp >> 4) * (NB * 16) + M * 16 + (kp & 15);
+        int8_t *gbase = dig + (size_t)gl * R * 2 * N + off;
+#pragma unroll
+        for (int p = 1; p <= (L ? L : 8); ++p) {
+            if (!L && p > l)
+                break;
+            int32_t d[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                d[k] = (int32_t)((w4[k] >> (32 - p * beta)) & bmask) - bhalf;
+#pragma unroll
+            for (int s = 0; s < (L ? S : 2); ++s) {
+                if (!L && s >= SS)
+                    break;
+                uint32_t pos = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    int32_t sd;
+                    if (s == SS - 1) {
+                        sd = d[k];
+                    } else {
+                        sd = ((d[k] + 64) & 127) - 64;
+                        d[k] = (d[k] - sd) >> 7;
+                    }
+                    pos |= ((uint32_t)sd & 0xFFu) << (8 * (3 - k));
+                }
+                // negate the four bytes at once: ~b + 1 per byte, the
+                // +1 kept inside each byte's low 7 bits
+                const uint32_t npos = ~pos;
+                uint32_t neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
+                               (npos & 0x80808080u);
+                int kb = ((c * l) + (p - 1)) * SS + s;
+                int8_t *base = gbase + (size_t)kb * 2 * N;
+                *reinterpret_cast<uint32_t *>(base) = pos;
+                *reinterpret_cast<uint32_t *>(base + N) = neg;
+            }
+        }
+    }
+}
 
 // L (gadget levels) and S (sub-digits per digit) are compile-time so the
 // digit loops unroll; L = 0 selects a generic build that reads l and S at
@@ -200,23 +277,32 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 
     // ---- key-window staging ----------------------------------------------
     // stage st = i*R + kb uses buffer st & 1; item = (array c'*4+q, word w).
-    // The global reads of the next stage are issued when a stage starts and
-    // their four byte-shifted LDS copies are written between the stage's
-    // MFMA groups.
+    // The global reads of stage st + PD are issued when stage st starts (for
+    // PD = 2 into far_*, whose previous contents, stage st + 1, are first
+    // moved into pre_*); the four byte-shifted LDS copies of stage st + 1
+    // are written from pre_* between stage st's MFMA groups.
     constexpr int ITEMS = 8 * CW;
     constexpr int PER_T = (ITEMS + I8_THREADS - 1) / I8_THREADS;
+    constexpr int PD = C::PD;
     uint32_t pre_lo[PER_T], pre_hi[PER_T];
-    auto prefetch = [&](int st) {
+    uint32_t far_lo[PD > 1 ? PER_T : 1], far_hi[PD > 1 ? PER_T : 1];
+    auto fetch = [&](int st, auto &lo, auto &hi) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
                               (size_t)st * 8 * EW;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             int item = tid + k * I8_THREADS;
-            if (item < ITEMS) {
-                int arr = item / CW, w = item - arr * CW;
-                pre_lo[k] = src[arr * EW + w];
-                pre_hi[k] = src[arr * EW + w + 1];
+            if (PD > 1) {
+                // every lane loads (the surplus ones a valid word they never
+                // store), so the registers in flight need no merge and are
+                // not waited for until they are used
+                item = min(item, ITEMS - 1);
+            } else if (item >= ITEMS) {
+                continue;
             }
+            int arr = item / CW, w = item - arr * CW;
+            lo[k] = src[arr * EW + w];
+            hi[k] = src[arr * EW + w + 1];
         }
     };
     auto stash_one = [&](int buf, int k) {
@@ -237,10 +323,12 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
             if (kk == k)
                 stash_one(buf, kk);
     };
-    prefetch(0);
+    fetch(0, pre_lo, pre_hi);
 #pragma unroll
     for (int k = 0; k < PER_T; ++k)
         stash_one(0, k);
+    if (PD > 1 && n * R > 1)
+        fetch(1, far_lo, far_hi);
     __syncthreads();
 
     // ---- per-lane constants ----------------------------------------------
@@ -274,71 +362,28 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     for (int i = 0; i < n; ++i) {
         __syncthreads();   // ACC of the previous step complete
         // ---- rotate, subtract, decompose into digit operands --------------
-        for (int item = tid; item < GPW * 2 * (N / 4); item += I8_THREADS) {
-            int gl = item / (2 * (N / 4));
-            int rem = item - gl * (2 * (N / 4));
-            int c = rem / (N / 4);
-            int m0 = 4 * (rem - c * (N / 4));
-            int e = ms[gl * (n + 1) + i];
-            const uint32_t *a = acc + (gl * 2 + c) * AST;
-            const int pm0 = ap(m0);           // the quad stays in one block
-            uint32_t w4[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                int t = (m0 + k - e) & (2 * N - 1);
-                uint32_t rv = a[ap(t & (N - 1))];
-                rv = t >= N ? 0u - rv : rv;
-                w4[k] = rv - a[pm0 + k] + dig_off;
-            }
-            // byte b of the dword holds coefficient m0 + 3 - b (reversed kappa)
-            int kap0 = m0 & 31, M = m0 >> 5;
-            int kp = 28 - kap0;                 // kappa' of byte 0
-            int off = (kp >> 4) * (NB * 16) + M * 16 + (kp & 15);
-            int8_t *gbase = dig + (size_t)gl * R * 2 * N + off;
-#pragma unroll
-            for (int p = 1; p <= (L ? L : 8); ++p) {
-                if (!L && p > l)
-                    break;
-                int32_t d[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    d[k] = (int32_t)((w4[k] >> (32 - p * beta)) & bmask) - bhalf;
-#pragma unroll
-                for (int s = 0; s < (L ? S : 2); ++s) {
-                    if (!L && s >= SS)
-                        break;
-                    uint32_t pos = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        int32_t sd;
-                        if (s == SS - 1) {
-                            sd = d[k];
-                        } else {
-                            sd = ((d[k] + 64) & 127) - 64;
-                            d[k] = (d[k] - sd) >> 7;
-                        }
-                        pos |= ((uint32_t)sd & 0xFFu) << (8 * (3 - k));
-                    }
-                    // negate the four bytes at once: ~b + 1 per byte, the
-                    // +1 kept inside each byte's low 7 bits
-                    const uint32_t npos = ~pos;
-                    uint32_t neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
-                                   (npos & 0x80808080u);
-                    int kb = ((c * l) + (p - 1)) * SS + s;
-                    int8_t *base = gbase + (size_t)kb * 2 * N;
-                    *reinterpret_cast<uint32_t *>(base) = pos;
-                    *reinterpret_cast<uint32_t *>(base + N) = neg;
-                }
-            }
-        }
+        decompose_acc<N, L, S, GPW, I8_THREADS>(acc, dig, ms, i, n, l, SS, R,
+                                                beta, dig_off, bmask, bhalf,
+                                                tid);
         __syncthreads();
 
         // ---- K loop: digit polynomials x block offsets --------------------
         for (int kb = 0; kb < R; ++kb) {
             const int st = i * R + kb;
             const bool more = st + 1 < n * R;
-            if (more)
-                prefetch(st + 1);
+            if constexpr (PD == 1) {
+                if (more)
+                    fetch(st + 1, pre_lo, pre_hi);
+            } else {
+#pragma unroll
+                for (int k = 0; k < PER_T; ++k) {
+                    pre_lo[k] = far_lo[k];
+                    pre_hi[k] = far_hi[k];
+                }
+                // unconditional (the last stages re-read the final window)
+                // for the same reason as the clamped items
+                fetch(min(st + 2, n * R - 1), far_lo, far_hi);
+            }
             const uint32_t *eb = ecop + (EBUF == 2 ? (st & 1) : 0) *
                                             (2 * 4 * 4 * CLEN) +
                                  cp * (4 * 4 * CLEN) + a_lane;
@@ -466,6 +511,336 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     }
 }
 
+// ---- latency mode: one tile's blind rotation over four workgroups --------
+//
+// A narrow batch leaves most CUs idle and each bootstrap's n CMux steps run
+// one after another on a single CU.  Here the step's GEMM of one column
+// tile (GPT = 1024/N bootstraps) is split over SPLIT_G = 4 workgroups on
+// four CUs: member m computes output component c' = m & 1 with key limbs
+// 2(m >> 1) and 2(m >> 1) + 1, over all digit polynomials and block offsets
+// (its 8 waves split the block offsets).  Every member keeps a full copy of
+// the accumulators; after each step the members exchange their partial
+// sums through global memory (64-bit words holding a 32-bit tag and the
+// 32-bit value, so a word is either the step's or stale as a whole) and
+// each adds all four into its copy.  The tag is the step plus a per-group
+// launch epoch (device-resident, advanced by member 0 when its group has
+// finished), so words left by an earlier launch never match.  Waits are
+// bounded: a member that waits longer than SPLIT_WAIT_TICKS of the 100 MHz
+// wall clock, or sees the context's error word set, sets that word and
+// stops; later launches on the context do nothing until cggi_ctx_check
+// clears it.  The members of a group are placed on one XCD (blocks of one
+// group are congruent mod 8), which keeps the exchange in one L2.
+constexpr int SPLIT_G = 4;
+constexpr int SPLIT_THREADS = 512;
+constexpr int SPLIT_RMAX = 12;           // digit polynomials per step
+constexpr unsigned long long SPLIT_WAIT_TICKS = 100000000ull;   // 1 s
+
+template <int N> struct SplitCfg {
+    static constexpr int NB = N / 32;
+    static constexpr int GPT = 1024 / N;    // bootstraps per column tile
+    static constexpr int ND = NB / 8;       // block offsets per wave
+    static constexpr int EW = (N + 64) / 4; // dwords per limb window
+    static constexpr int CW = N / 4 + 8;    // dwords of a shifted copy used
+    static constexpr int CLEN = N / 4 + 8;  // stride of a shifted copy
+    static constexpr int AST = N + N / 32;  // padded accumulator row
+    static constexpr int WORDS = GPT * N;   // partial words per member
+};
+
+template <int N>
+static size_t split_smem_bytes(int R, int n)
+{
+    using C = SplitCfg<N>;
+    size_t b = (size_t)R * 8 * C::CLEN * 4          // key windows of a step
+               + (size_t)C::GPT * 3 * C::AST * 4    // accumulators + partial
+               + (size_t)C::GPT * R * 2 * N;        // digit operands
+    return b + (((size_t)C::GPT * (n + 1) * 2 + 15) & ~(size_t)15);
+}
+
+template <int N, int L, int S>
+__global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
+    const int8_t *__restrict__ key, const uint32_t *__restrict__ in,
+    const uint32_t *__restrict__ testv, uint32_t *__restrict__ out, int B,
+    const int32_t *__restrict__ d_count, unsigned long long *xb,
+    uint32_t *epoch, uint32_t *err, int n, int beta, int l_rt, int S_rt)
+{
+    using C = SplitCfg<N>;
+    constexpr int NB = C::NB, GPT = C::GPT, ND = C::ND, EW = C::EW;
+    constexpr int CW = C::CW, CLEN = C::CLEN, AST = C::AST;
+    constexpr int WORDS = C::WORDS, T = SPLIT_THREADS;
+    constexpr int LOG2_2N = __builtin_ctz(2 * N);
+    const int l = L ? L : l_rt;
+    const int SS = L ? S : S_rt;
+    const int R = 2 * l * SS;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);   // [R][2][4][CLEN]
+    uint32_t *acc = ecop + R * 8 * CLEN;                    // [GPT][2][AST]
+    uint32_t *part = acc + GPT * 2 * AST;                   // [GPT][AST]
+    int8_t *dig = reinterpret_cast<int8_t *>(part + GPT * AST);
+    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPT * R * 2 * N);
+    __shared__ int s_stop;
+    __shared__ uint32_t s_ep;
+    auto ap = [](int j) { return j + (j >> 5); };
+
+    // block -> (group, member): the four members of a group share b mod 8
+    const int x8 = blockIdx.x & 7, q8 = blockIdx.x >> 3;
+    const int member = q8 & (SPLIT_G - 1);
+    const int grp = (q8 / SPLIT_G) * 8 + x8;
+    int count = B;
+    if (d_count)
+        count = min(count, *d_count);
+    const int g0 = grp * GPT;
+    if (g0 >= count)
+        return;
+    const int cp = member & 1, q0 = 2 * (member >> 1);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+
+    if (tid == 0) {
+        s_stop = __hip_atomic_load(err, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) != 0;
+        s_ep = __hip_atomic_load(&epoch[grp], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // ---- modulus switch, ACC = (0, X^(2N - b~) v), partial = 0 -----------
+    for (int idx = tid; idx < GPT * (n + 1); idx += T) {
+        int gl = idx / (n + 1), i = idx - gl * (n + 1);
+        int g = g0 + gl;
+        uint32_t u = g < count ? in[(size_t)g * (n + 1) + i] : 0u;
+        ms[idx] = (uint16_t)modswitch(u, LOG2_2N);
+    }
+    for (int idx = tid; idx < GPT * AST; idx += T)
+        part[idx] = 0u;
+    __syncthreads();
+    if (s_stop)
+        return;
+    const uint32_t ep = s_ep;
+    for (int idx = tid; idx < GPT * N; idx += T) {
+        int gl = idx / N, m = idx - gl * N;
+        int e = (2 * N - ms[gl * (n + 1) + n]) & (2 * N - 1);
+        uint32_t v = testv ? testv[m] : (1u << 29);
+        int t = m + e;
+        if (t >= 2 * N) {
+            t -= 2 * N;
+        } else if (t >= N) {
+            t -= N;
+            v = 0u - v;
+        }
+        acc[(gl * 2 + 0) * AST + ap(t)] = 0u;
+        acc[(gl * 2 + 1) * AST + ap(t)] = v;
+    }
+
+    // ---- key windows of this member's (c', limb pair), one step at a time:
+    // step i + 1's are read into registers during step i - 1 and written to
+    // LDS (four byte-shifted copies) while step i's partials are exchanged
+    constexpr int RMAX = L ? 2 * L * S : SPLIT_RMAX;
+    constexpr int PER_T = (RMAX * 2 * CW + T - 1) / T;
+    const int items = R * 2 * CW;
+    uint32_t pre_lo[PER_T], pre_hi[PER_T];
+    auto fetch = [&](int i) {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
+                              (size_t)i * R * 8 * EW;
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            // surplus lanes re-read the last word (never stored)
+            int item = min(tid + k * T, items - 1);
+            int kb = item / (2 * CW), rem = item - kb * (2 * CW);
+            int qq = rem / CW, w = rem - qq * CW;
+            const uint32_t *sp =
+                src + ((size_t)kb * 8 + cp * 4 + q0 + qq) * EW + w;
+            pre_lo[k] = sp[0];
+            pre_hi[k] = sp[1];
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            int item = tid + k * T;
+            if (item < items) {
+                int kb = item / (2 * CW), rem = item - kb * (2 * CW);
+                int qq = rem / CW, w = rem - qq * CW;
+                uint32_t *d = ecop + (kb * 2 + qq) * 4 * CLEN + w;
+                d[0] = pre_lo[k];
+                d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
+                d[2 * CLEN] =
+                    __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
+                d[3 * CLEN] =
+                    __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
+            }
+        }
+    };
+    fetch(0);
+    stash();
+    if (n > 1)
+        fetch(1);
+
+    // ---- per-lane constants ----------------------------------------------
+    const int rho = lane & 31, hh = lane >> 5;
+    const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
+    const int glc = rho / NB, Jc = rho % NB;   // column -> bootstrap, block
+    const int dl0 = wave * ND;
+    const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
+    uint32_t dig_off = round_off;
+    for (int p = 1; p <= l; ++p)
+        dig_off += (1u << (beta - 1)) << (32 - p * beta);
+    const uint32_t bmask = (1u << beta) - 1u;
+    const int32_t bhalf = 1 << (beta - 1);
+    unsigned long long *xg = xb + (size_t)grp * 2 * SPLIT_G * WORDS;
+    const int8_t *dbase = dig + (size_t)glc * R * 2 * N + hh * (NB * 16);
+    constexpr int PW = WORDS / T;                 // words per thread
+
+    for (int i = 0; i < n; ++i) {
+        __syncthreads();   // ACC and this step's key windows complete
+        if (s_stop)
+            break;
+        decompose_acc<N, L, S, GPT, T>(acc, dig, ms, i, n, l, SS, R, beta,
+                                       dig_off, bmask, bhalf, tid);
+        __syncthreads();
+
+        // ---- K loop over (digit polynomial, block offset) ---------------
+        auto load = [&](int idx, v4i (&af)[2], v4i &bf) {
+            const int kb = idx / ND, dl = dl0 + idx % ND;
+            const uint32_t *eb = ecop + kb * 8 * CLEN + a_lane + 8 * dl;
+#pragma unroll
+            for (int qq = 0; qq < 2; ++qq) {
+                const uint32_t *apq = eb + qq * 4 * CLEN;
+                af[qq][0] = (int)apq[0];
+                af[qq][1] = (int)apq[1];
+                af[qq][2] = (int)apq[2];
+                af[qq][3] = (int)apq[3];
+            }
+            const int Mb = (Jc - dl) & (NB - 1);
+            const int sg = Jc < dl ? N : 0;
+            bf = *reinterpret_cast<const v4i *>(dbase + (size_t)kb * 2 * N +
+                                                sg + Mb * 16);
+        };
+        const int K = R * ND;                     // even: R is even
+        v16i C0 = {}, C1 = {};
+        v4i af[2][2], bf[2];
+        load(0, af[0], bf[0]);
+#pragma unroll 1
+        for (int idx = 0; idx < K; idx += 2) {
+            load(idx + 1, af[1], bf[1]);
+            C0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[0][0], bf[0], C0,
+                                                       0, 0, 0);
+            C1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[0][1], bf[0], C1,
+                                                       0, 0, 0);
+            if (idx + 2 < K)
+                load(idx + 2, af[0], bf[0]);
+            C0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[1][0], bf[1], C0,
+                                                       0, 0, 0);
+            C1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[1][1], bf[1], C1,
+                                                       0, 0, 0);
+        }
+        // ---- fold the two limbs, add this wave's block offsets ----------
+        {
+            uint32_t *pp = part + glc * AST + 33 * Jc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                int row = 8 * (v >> 2) + 4 * hh + (v & 3);
+                uint32_t xv = (uint32_t)C0[v] + ((uint32_t)C1[v] << 8);
+                atomicAdd(&pp[row], xv << (8 * q0));
+            }
+        }
+        __syncthreads();   // partial complete; key windows free
+
+        // ---- publish the partial (tag = epoch * 1024 + step + 1) --------
+        const unsigned long long tag =
+            (unsigned long long)(ep * 1024u + (uint32_t)i + 1u) << 32;
+        unsigned long long *xw =
+            xg + ((size_t)(i & 1) * SPLIT_G + member) * WORDS;
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            const int m = tid + k * T;
+            const int gl = m / N, j = m - gl * N;
+            uint32_t *pp = &part[gl * AST + ap(j)];
+            __hip_atomic_store(&xw[m], tag | *pp, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            *pp = 0u;
+        }
+        if (i + 1 < n) {
+            stash();
+            if (i + 2 < n)
+                fetch(i + 2);
+        }
+        // ---- gather the four partials of both components ----------------
+        const unsigned long long *xr = xg + (size_t)(i & 1) * SPLIT_G * WORDS;
+        unsigned long long wv[SPLIT_G][PW];
+#pragma unroll
+        for (int mb = 0; mb < SPLIT_G; ++mb)
+#pragma unroll
+            for (int k = 0; k < PW; ++k)
+                wv[mb][k] = __hip_atomic_load(&xr[mb * WORDS + tid + k * T],
+                                              __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+        bool failed = false;
+        const unsigned long long t_start = wall_clock64();
+        for (int it = 1;; ++it) {
+            bool ok = true;
+#pragma unroll
+            for (int mb = 0; mb < SPLIT_G; ++mb)
+#pragma unroll
+                for (int k = 0; k < PW; ++k)
+                    ok = ok && (wv[mb][k] & 0xFFFFFFFF00000000ull) == tag;
+            if (ok)
+                break;
+#pragma unroll
+            for (int mb = 0; mb < SPLIT_G; ++mb)
+#pragma unroll
+                for (int k = 0; k < PW; ++k)
+                    if ((wv[mb][k] & 0xFFFFFFFF00000000ull) != tag)
+                        wv[mb][k] = __hip_atomic_load(
+                            &xr[mb * WORDS + tid + k * T], __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+            if ((it & 15) == 0 &&
+                (__hip_atomic_load(err, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                 wall_clock64() - t_start > SPLIT_WAIT_TICKS)) {
+                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                failed = true;
+                break;
+            }
+        }
+        if (failed) {
+            s_stop = 1;
+        } else {
+#pragma unroll
+            for (int k = 0; k < PW; ++k) {
+                const int m = tid + k * T;
+                const int gl = m / N, j = m - gl * N;
+#pragma unroll
+                for (int c2 = 0; c2 < 2; ++c2)
+                    acc[(gl * 2 + c2) * AST + ap(j)] +=
+                        (uint32_t)wv[c2][k] + (uint32_t)wv[c2 + 2][k];
+            }
+        }
+    }
+    __syncthreads();
+    if (s_stop || member != 0)
+        return;
+    if (tid == 0)
+        __hip_atomic_fetch_add(&epoch[grp], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+
+    // ---- sample extraction (member 0) ----------------------------------------
+    for (int idx = tid; idx < GPT * (N + 1); idx += T) {
+        int gl = idx / (N + 1), j = idx - gl * (N + 1);
+        int g = g0 + gl;
+        if (g >= count)
+            continue;
+        const uint32_t *a = acc + gl * 2 * AST;
+        uint32_t v;
+        if (j == 0)
+            v = a[0];
+        else if (j < N)
+            v = 0u - a[ap(N - j)];
+        else
+            v = a[AST];
+        out[(size_t)g * (N + 1) + j] = v;
+    }
+}
+
 } // namespace
 
 size_t int8_smem_bytes(int N, int R, int n)
@@ -477,6 +852,67 @@ size_t int8_smem_bytes(int N, int R, int n)
     case 2048: return I8Smem<2048>::total(R, n);
     default: return (size_t)-1;
     }
+}
+
+// Latency mode set-up for one kernel instantiation: the largest number of
+// tile groups whose workgroups are all resident at once (so the members'
+// waits on each other always end), and the exchange buffers for them.
+template <int N, int L, int S>
+static int split_setup_t(Ctx *c, hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    const size_t smem = split_smem_bytes<N>(sh.R, sh.n);
+    // (the kernel also holds 8 bytes of static LDS)
+    if (sh.R > SPLIT_RMAX || smem + 64 > 160 * 1024)
+        return CGGI_OK;                       // latency mode unavailable
+    const void *fn =
+        reinterpret_cast<const void *>(&k_bootstrap_int8_split<N, L, S>);
+    CGGI_HIP_TRY(hipFuncSetAttribute(
+        fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    int occ = 0;
+    CGGI_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, fn, SPLIT_THREADS, smem));
+    const int groups = c->cus * occ / SPLIT_G;
+    if (groups < 1)
+        return CGGI_OK;
+    const size_t xwords = (size_t)groups * 2 * SPLIT_G * SplitCfg<N>::WORDS;
+    if (hipMalloc(&c->x_buf, xwords * 8) != hipSuccess ||
+        hipMalloc(&c->x_epoch, (size_t)groups * 4) != hipSuccess ||
+        hipMalloc(&c->x_err, 4) != hipSuccess)
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the latency-mode "
+                                       "exchange buffers failed");
+    CGGI_HIP_TRY(hipMemsetAsync(c->x_buf, 0, xwords * 8, s));
+    CGGI_HIP_TRY(hipMemsetAsync(c->x_epoch, 0, (size_t)groups * 4, s));
+    CGGI_HIP_TRY(hipMemsetAsync(c->x_err, 0, 4, s));
+    c->x_words = xwords;
+    c->split_groups = groups;
+    return CGGI_OK;
+}
+
+template <int N>
+static int split_setup(Ctx *c, hipStream_t s)
+{
+    if constexpr (N > 1024) {
+        return CGGI_OK;
+    } else {
+        const Shape &sh = c->sh;
+        if (sh.l == 3 && sh.S == 1)
+            return split_setup_t<N, 3, 1>(c, s);
+        if (sh.l == 2 && sh.S == 2)
+            return split_setup_t<N, 2, 2>(c, s);
+        return split_setup_t<N, 0, 0>(c, s);
+    }
+}
+
+int int8_split_reset(Ctx *c)
+{
+    if (!c->x_buf)
+        return CGGI_OK;
+    CGGI_HIP_TRY(hipMemset(c->x_buf, 0, c->x_words * 8));
+    CGGI_HIP_TRY(hipMemset(c->x_epoch, 0, (size_t)c->split_groups * 4));
+    CGGI_HIP_TRY(hipMemset(c->x_err, 0, 4));
+    CGGI_HIP_TRY(hipDeviceSynchronize());
+    return CGGI_OK;
 }
 
 template <int N>
@@ -494,7 +930,7 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
                        c->bsk_i8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
-    return CGGI_OK;
+    return split_setup<N>(c, s);
 }
 
 int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
@@ -531,14 +967,35 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     return CGGI_OK;
 }
 
-// Column tiles per workgroup for a batch of (at most) B bootstraps: the
-// fewest that still fit the batch into one wave of workgroups over the CUs.
+template <int N, int L, int S>
+static int launch_split(const Ctx *c, const uint32_t *in,
+                        const uint32_t *testv, uint32_t *out, int B,
+                        const int32_t *d_count, hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    const int groups = (B + SplitCfg<N>::GPT - 1) / SplitCfg<N>::GPT;
+    const int grid = (groups + 7) / 8 * 8 * SPLIT_G;
+    hipLaunchKernelGGL((k_bootstrap_int8_split<N, L, S>), dim3(grid),
+                       dim3(SPLIT_THREADS), split_smem_bytes<N>(sh.R, sh.n),
+                       s, c->bsk_i8, in, testv, out, B, d_count, c->x_buf,
+                       c->x_epoch, c->x_err, sh.n, sh.beta, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+// Batches of at most split_groups column tiles (bounded by B, the most the
+// launch can hold) run in latency mode when it is on; otherwise the column
+// tiles per workgroup are the fewest that still fit the batch into one wave
+// of workgroups over the CUs.
 template <int N, int L, int S>
 static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
                             const uint32_t *testv, uint32_t *out, int B,
                             const int32_t *d_count, hipStream_t s)
 {
     if constexpr (N <= 1024) {
+        if (c->split_on && c->split_groups > 0 &&
+            (B + SplitCfg<N>::GPT - 1) / SplitCfg<N>::GPT <= c->split_groups)
+            return launch_split<N, L, S>(c, in, testv, out, B, d_count, s);
         const long tiles = (B + I8Cfg<N>::GPT - 1) / I8Cfg<N>::GPT;
         if (tiles <= c->cus)
             return launch_bs_int8_t<N, L, S, 1>(c, in, testv, out, B, d_count,

@@ -38,6 +38,13 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
+    // INT8 latency mode (one tile over four workgroups, N <= 1024)
+    bool split_on = true;         // cggi_ctx_latency_mode
+    int split_groups = 0;         // most tile groups per launch (0: off)
+    unsigned long long *x_buf = nullptr; // [groups][2][4][1024] tagged words
+    size_t x_words = 0;
+    uint32_t *x_epoch = nullptr;  // [groups] launch epoch per group slot
+    uint32_t *x_err = nullptr;    // [1] set when a member's wait timed out
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
     int ks_ksj = 0;               // 32-slot K-steps per j
@@ -82,6 +89,9 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s);
 int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
                    uint32_t *out, int B, const int32_t *d_count,
                    hipStream_t s);
+// Re-zeroes the latency-mode exchange buffers, epochs and error word
+// (synchronous).
+int int8_split_reset(Ctx *c);
 
 // Key switch.  in_a/in_b: optional second input added before switching
 // (MUX combine); the plain batch call passes null maps.

@@ -1,0 +1,153 @@
+"""Latency mode of the int8 form: a narrow batch runs each column tile's
+blind rotation on four workgroups that exchange partial products after
+every CMux step.  Bit-exact against the oracle and the NTT form, identical
+to the one-workgroup kernel, at every N <= 1024 and digit shape (specialised
+and generic builds), over partial tiles, repeated launches (launch epochs)
+and HIP-graph replays of a whole narrow circuit."""
+import concurrent.futures as cf
+import dataclasses
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2306_11006_amd import arith, inputs, params
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 4)
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_bs(ctx, form, cts):
+    import torch
+    from paper_2306_11006_amd import cggi
+    out = ctx.bootstrap(form, cggi.to_device(cts))
+    torch.cuda.synchronize()
+    return cggi.to_host(out)
+
+
+def make_ctx(p, seed):
+    from paper_2306_11006_amd import cggi
+    bsk, ksk = inputs.uniform_keys(p, seed)
+    ctx = cggi.Context(p, cggi.to_device(bsk), cggi.to_device(ksk))
+    return bsk, ksk, ctx
+
+
+CASES = [
+    # (parameter set, batch sizes): N = 1024 (l=3, S=1 build), N = 256 with
+    # Bg = 2^8 (two sub-digits, the l=2 S=2 build, four bootstraps per tile)
+    (params.DEFAULT, (1, 3, 64)),
+    (params.TOY, (1, 5, 255)),
+    (dataclasses.replace(params.DEFAULT, name="n512_N512", n=512, N=512),
+     (2, 9)),
+    # generic build (digit loops with run-time bounds): l = 2 levels of 2^7
+    (dataclasses.replace(params.DEFAULT, name="bg7_l2", l=2), (1, 7)),
+]
+
+
+@pytest.mark.parametrize("p,batches", CASES, ids=[c[0].name for c in CASES])
+def test_latency_mode_bit_exact(O, p, batches):
+    from paper_2306_11006_amd import cggi
+    bsk, ksk, ctx = make_ctx(p, 7100 + p.N)
+    groups = ctx.latency_groups()
+    assert groups >= 1, p.name
+    for B in batches:
+        tiles = -(-B // (1024 // p.N))
+        assert tiles <= groups, (B, groups)
+        cts = inputs.uniform_lwe(p, 7200 + B, B)
+        say(f"latency mode {p.name} B={B} tiles={tiles} (limit {groups})")
+        got = run_bs(ctx, "int8", cts)
+        ctx.check()
+        ntt = run_bs(ctx, "ntt", cts)
+        assert np.array_equal(got, ntt), (p.name, B)
+        ctx.latency_mode(False)
+        one = run_bs(ctx, "int8", cts)
+        ctx.latency_mode(True)
+        assert np.array_equal(got, one), (p.name, B)
+        pick = sorted({0, B - 1, B // 2})
+        with cf.ThreadPoolExecutor(THREADS) as ex:
+            want = list(ex.map(lambda i: O.bootstrap(p, bsk, cts[i]), pick))
+        for i, wv in zip(pick, want):
+            assert np.array_equal(got[i], wv), (p.name, B, i)
+    ctx.close()
+
+
+def test_latency_mode_limits():
+    """Off -> no groups; N = 2048 has no latency mode; a batch one tile
+    beyond the limit takes the one-workgroup kernel (same result)."""
+    from paper_2306_11006_amd import cggi
+    p = params.DEFAULT
+    bsk, ksk, ctx = make_ctx(p, 7300)
+    groups = ctx.latency_groups()
+    ctx.latency_mode(False)
+    assert ctx.latency_groups() == 0
+    ctx.latency_mode(True)
+    assert ctx.latency_groups() == groups
+    cts = inputs.uniform_lwe(p, 7301, groups + 1)
+    a = run_bs(ctx, "int8", cts)
+    b = run_bs(ctx, "ntt", cts)
+    assert np.array_equal(a, b)
+    ctx.check()
+    ctx.close()
+    bl, kl = inputs.uniform_keys(params.LARGE, 7302)
+    cl = cggi.Context(params.LARGE, cggi.to_device(bl), cggi.to_device(kl),
+                      forms=("int8",))
+    assert cl.latency_groups() == 0
+    cl.close()
+
+
+def test_latency_mode_repeated_launches_and_graph():
+    """Back-to-back launches of varying width advance the per-group epochs;
+    a narrow circuit (32-bit prefix adder: its first level of 64 gates takes
+    the one-workgroup kernel, the six levels of 15 to 32 gates latency mode)
+    captured as one HIP graph and replayed three times, with eager work
+    between the replays, equals the eager run every time."""
+    import torch
+    from paper_2306_11006_amd import cggi
+    from paper_2306_11006_amd.circuit import LevelledCircuit
+    p = params.DEFAULT
+    bsk, ksk, ctx = make_ctx(p, 7400)
+    groups = ctx.latency_groups()
+    base = inputs.uniform_lwe(p, 7401, groups)
+    ref = run_bs(ctx, "ntt", base)
+    for B in (groups, 1, groups // 2, 2, groups):
+        say(f"repeated launch B={B}")
+        got = run_bs(ctx, "int8", base[:B])
+        assert np.array_equal(got, ref[:B]), B
+    ctx.check()
+
+    nl, io = arith.adder(32, "prefix")
+    circ = LevelledCircuit(nl.array(), nl.n_wires)
+    narrow = [w for w in circ.widths if 2 * w <= groups]
+    assert len(narrow) == circ.n_levels - 1, (circ.widths, groups)
+    wires = np.zeros((nl.n_wires, p.n + 1), dtype=np.uint32)
+    ins = list(io["a"]) + list(io["b"])
+    wires[ins] = inputs.uniform_lwe(p, 7402, len(ins))
+    eager = cggi.to_device(wires)
+    say("narrow circuit eager")
+    circ.run(ctx, "int8", eager)
+    torch.cuda.synchronize()
+    want = cggi.to_host(eager)
+    ntt = cggi.to_device(wires)
+    circ.run(ctx, "ntt", ntt)
+    torch.cuda.synchronize()
+    assert np.array_equal(cggi.to_host(ntt), want)
+    gw = cggi.to_device(wires)
+    graph = circ.capture(ctx, "int8", gw)
+    for rep in range(3):
+        say(f"narrow circuit graph replay {rep}")
+        gw.copy_(cggi.to_device(wires))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(cggi.to_host(gw), want), rep
+        # eager latency-mode work between replays
+        got = run_bs(ctx, "int8", base[:3])
+        assert np.array_equal(got, ref[:3])
+    ctx.check()
+    del graph
+    ctx.close()
