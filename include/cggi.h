@@ -211,7 +211,7 @@ int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
  * call's B (2G for a level of G gates) needs at most *groups tiles, where
  * cggi_ctx_latency_groups reports the context's limit (every workgroup of
  * such a launch is resident at once; 0 when latency mode is off or
- * unavailable: N = 2048, more than 12 digit polynomials, or LDS).  It is on
+ * unavailable: N = 2048, more than 8 digit polynomials, or LDS).  It is on
  * by default; cggi_ctx_latency_mode(ctx, 0) turns it off, e.g. when other
  * streams keep the GPU's CUs busy, since the four workgroups of a tile wait
  * for each other.  Each wait is bounded (1 s): on a time-out the kernel

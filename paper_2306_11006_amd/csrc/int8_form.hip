@@ -88,6 +88,16 @@ template <int N, int T = 4> struct I8Cfg {
     static constexpr int ECOP_DW = EBUF * 2 * 4 * 4 * CLEN; // buf, c', q, sigma
 };
 
+// Workgroup barrier ordering LDS only.  Inside the CMux loops the threads
+// of a workgroup share nothing through global memory, and a full
+// __syncthreads would also wait for the key reads issued ahead of use.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
 {
     return (u + (1u << (31 - log2_2n))) >> (32 - log2_2n);
@@ -145,19 +155,21 @@ struct I8Smem {
 // Fig. 1, the decomposition of the CMux step; Section 2.2).
 // Layout of dig: [GPW][R][2 signs][N] bytes; within a polynomial the 16
 // bytes of each lane's B operand hold one 32-block's kappa in reverse.
-template <int N, int L, int S, int GPW, int THREADS>
+// NC = 1 decomposes component c_sel only, into rows 0 .. l*SS - 1 (R then
+// counts the rows per bootstrap of that layout).
+template <int N, int L, int S, int GPW, int THREADS, int NC = 2>
 __device__ __forceinline__ void decompose_acc(
     const uint32_t *acc, int8_t *dig, const uint16_t *ms, int i, int n, int l,
     int SS, int R, int beta, uint32_t dig_off, uint32_t bmask, int32_t bhalf,
-    int tid)
+    int tid, int c_sel = 0)
 {
     constexpr int NB = N / 32, AST = N + N / 32;
     auto ap = [](int j) { return j + (j >> 5); };
-    for (int item = tid; item < GPW * 2 * (N / 4); item += THREADS) {
-        int gl = item / (2 * (N / 4));
-        int rem = item - gl * (2 * (N / 4));
-        int c = rem / (N / 4);
-        int m0 = 4 * (rem - c * (N / 4));
+    for (int item = tid; item < GPW * NC * (N / 4); item += THREADS) {
+        int gl = item / (NC * (N / 4));
+        int rem = item - gl * (NC * (N / 4));
+        int c = NC == 2 ? rem / (N / 4) : c_sel;
+        int m0 = 4 * (NC == 2 ? rem - c * (N / 4) : rem);
         int e = ms[gl * (n + 1) + i];
         const uint32_t *a = acc + (gl * 2 + c) * AST;
         const int pm0 = ap(m0);           // the quad stays in one block
@@ -203,7 +215,7 @@ __device__ __forceinline__ void decompose_acc(
                 const uint32_t npos = ~pos;
                 uint32_t neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
                                (npos & 0x80808080u);
-                int kb = ((c * l) + (p - 1)) * SS + s;
+                int kb = ((NC == 2 ? c * l : 0) + (p - 1)) * SS + s;
                 int8_t *base = gbase + (size_t)kb * 2 * N;
                 *reinterpret_cast<uint32_t *>(base) = pos;
                 *reinterpret_cast<uint32_t *>(base + N) = neg;
@@ -360,12 +372,12 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     v16i Cacc[WT][LPW];
 
     for (int i = 0; i < n; ++i) {
-        __syncthreads();   // ACC of the previous step complete
+        lds_barrier();   // ACC of the previous step complete
         // ---- rotate, subtract, decompose into digit operands --------------
         decompose_acc<N, L, S, GPW, I8_THREADS>(acc, dig, ms, i, n, l, SS, R,
                                                 beta, dig_off, bmask, bhalf,
                                                 tid);
-        __syncthreads();
+        lds_barrier();
 
         // ---- K loop: digit polynomials x block offsets --------------------
         for (int kb = 0; kb < R; ++kb) {
@@ -464,13 +476,13 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                 for (int k = ND - STASH0; k < PER_T; ++k)
                     stash_dyn((st + 1) & 1, k);
             }
-            __syncthreads();
+            lds_barrier();
             if (EBUF == 1 && more) {
                 // single window buffer: refill it once every wave is done
 #pragma unroll
                 for (int k = 0; k < PER_T; ++k)
                     stash_one(0, k);
-                __syncthreads();
+                lds_barrier();
             }
         }
 
@@ -516,11 +528,13 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 // A narrow batch leaves most CUs idle and each bootstrap's n CMux steps run
 // one after another on a single CU.  Here the step's GEMM of one column
 // tile (GPT = 1024/N bootstraps) is split over SPLIT_G = 4 workgroups on
-// four CUs: member m computes output component c' = m & 1 with key limbs
-// 2(m >> 1) and 2(m >> 1) + 1, over all digit polynomials and block offsets
-// (its 8 waves split the block offsets).  Every member keeps a full copy of
-// the accumulators; after each step the members exchange their partial
-// sums through global memory (64-bit words holding a 32-bit tag and the
+// four CUs along the 2 x 2 block structure of the external product: member
+// m adds the digits of accumulator component c = m >> 1 times the key rows
+// of that component into output component c' = m & 1, for all four key
+// limbs (its 8 waves split the block offsets), so it decomposes only its
+// own input component.  Every member keeps a full copy of the
+// accumulators; after each step the members exchange their partial sums
+// through global memory (64-bit words holding a 32-bit tag and the
 // 32-bit value, so a word is either the step's or stale as a whole) and
 // each adds all four into its copy.  The tag is the step plus a per-group
 // launch epoch (device-resident, advanced by member 0 when its group has
@@ -532,7 +546,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 // group are congruent mod 8), which keeps the exchange in one L2.
 constexpr int SPLIT_G = 4;
 constexpr int SPLIT_THREADS = 512;
-constexpr int SPLIT_RMAX = 12;           // digit polynomials per step
+constexpr int SPLIT_RMAX = 8;            // digit polynomials per step
 constexpr unsigned long long SPLIT_WAIT_TICKS = 100000000ull;   // 1 s
 
 template <int N> struct SplitCfg {
@@ -552,7 +566,7 @@ static size_t split_smem_bytes(int R, int n)
     using C = SplitCfg<N>;
     size_t b = (size_t)R * 8 * C::CLEN * 4          // key windows of a step
                + (size_t)C::GPT * 3 * C::AST * 4    // accumulators + partial
-               + (size_t)C::GPT * R * 2 * N;        // digit operands
+               + (size_t)C::GPT * (R / 2) * 2 * N;  // digit operands
     return b + (((size_t)C::GPT * (n + 1) * 2 + 15) & ~(size_t)15);
 }
 
@@ -571,13 +585,15 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int l = L ? L : l_rt;
     const int SS = L ? S : S_rt;
     const int R = 2 * l * SS;
+    const int RH = l * SS;                 // digit rows of one component
 
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);   // [R][2][4][CLEN]
+    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);  // [RH][4][4][CLEN]
     uint32_t *acc = ecop + R * 8 * CLEN;                    // [GPT][2][AST]
     uint32_t *part = acc + GPT * 2 * AST;                   // [GPT][AST]
     int8_t *dig = reinterpret_cast<int8_t *>(part + GPT * AST);
-    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPT * R * 2 * N);
+    uint16_t *ms =
+        reinterpret_cast<uint16_t *>(dig + (size_t)GPT * RH * 2 * N);
     __shared__ int s_stop;
     __shared__ uint32_t s_ep;
     auto ap = [](int j) { return j + (j >> 5); };
@@ -592,7 +608,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int g0 = grp * GPT;
     if (g0 >= count)
         return;
-    const int cp = member & 1, q0 = 2 * (member >> 1);
+    const int cp = member & 1, ch = member >> 1;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 
@@ -630,24 +646,25 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         acc[(gl * 2 + 1) * AST + ap(t)] = v;
     }
 
-    // ---- key windows of this member's (c', limb pair), one step at a time:
-    // step i + 1's are read into registers during step i - 1 and written to
-    // LDS (four byte-shifted copies) while step i's partials are exchanged
+    // ---- key windows of this member's rows (digit rows of component ch,
+    // output component c', four limbs), one step at a time:
+    // step i + 1's are read while step i's partials are exchanged (the two
+    // latencies overlap) and then written to LDS in four byte-shifted
+    // copies; no read stays in flight from one step into the next
     constexpr int RMAX = L ? 2 * L * S : SPLIT_RMAX;
     constexpr int PER_T = (RMAX * 2 * CW + T - 1) / T;
-    const int items = R * 2 * CW;
+    const int items = RH * 4 * CW;
     uint32_t pre_lo[PER_T], pre_hi[PER_T];
     auto fetch = [&](int i) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
-                              (size_t)i * R * 8 * EW;
+                              ((size_t)i * R + ch * RH) * 8 * EW;
 #pragma unroll
         for (int k = 0; k < PER_T; ++k) {
             // surplus lanes re-read the last word (never stored)
             int item = min(tid + k * T, items - 1);
-            int kb = item / (2 * CW), rem = item - kb * (2 * CW);
-            int qq = rem / CW, w = rem - qq * CW;
-            const uint32_t *sp =
-                src + ((size_t)kb * 8 + cp * 4 + q0 + qq) * EW + w;
+            int kb = item / (4 * CW), rem = item - kb * (4 * CW);
+            int q = rem / CW, w = rem - q * CW;
+            const uint32_t *sp = src + ((size_t)kb * 8 + cp * 4 + q) * EW + w;
             pre_lo[k] = sp[0];
             pre_hi[k] = sp[1];
         }
@@ -657,9 +674,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         for (int k = 0; k < PER_T; ++k) {
             int item = tid + k * T;
             if (item < items) {
-                int kb = item / (2 * CW), rem = item - kb * (2 * CW);
-                int qq = rem / CW, w = rem - qq * CW;
-                uint32_t *d = ecop + (kb * 2 + qq) * 4 * CLEN + w;
+                int kb = item / (4 * CW), rem = item - kb * (4 * CW);
+                int q = rem / CW, w = rem - q * CW;
+                uint32_t *d = ecop + (kb * 4 + q) * 4 * CLEN + w;
                 d[0] = pre_lo[k];
                 d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
                 d[2 * CLEN] =
@@ -671,8 +688,6 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     };
     fetch(0);
     stash();
-    if (n > 1)
-        fetch(1);
 
     // ---- per-lane constants ----------------------------------------------
     const int rho = lane & 31, hh = lane >> 5;
@@ -686,63 +701,69 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const uint32_t bmask = (1u << beta) - 1u;
     const int32_t bhalf = 1 << (beta - 1);
     unsigned long long *xg = xb + (size_t)grp * 2 * SPLIT_G * WORDS;
-    const int8_t *dbase = dig + (size_t)glc * R * 2 * N + hh * (NB * 16);
+    const int8_t *dbase = dig + (size_t)glc * RH * 2 * N + hh * (NB * 16);
     constexpr int PW = WORDS / T;                 // words per thread
 
     for (int i = 0; i < n; ++i) {
-        __syncthreads();   // ACC and this step's key windows complete
+        lds_barrier();   // ACC and this step's key windows complete
         if (s_stop)
             break;
-        decompose_acc<N, L, S, GPT, T>(acc, dig, ms, i, n, l, SS, R, beta,
-                                       dig_off, bmask, bhalf, tid);
-        __syncthreads();
+        decompose_acc<N, L, S, GPT, T, 1>(acc, dig, ms, i, n, l, SS, RH,
+                                          beta, dig_off, bmask, bhalf, tid,
+                                          ch);
+        lds_barrier();
 
-        // ---- K loop over (digit polynomial, block offset) ---------------
-        auto load = [&](int idx, v4i (&af)[2], v4i &bf) {
+        // ---- K loop over (digit row of component ch, block offset) ------
+        auto load = [&](int idx, v4i (&af)[4], v4i &bf) {
             const int kb = idx / ND, dl = dl0 + idx % ND;
-            const uint32_t *eb = ecop + kb * 8 * CLEN + a_lane + 8 * dl;
+            const uint32_t *eb = ecop + kb * 16 * CLEN + a_lane + 8 * dl;
 #pragma unroll
-            for (int qq = 0; qq < 2; ++qq) {
-                const uint32_t *apq = eb + qq * 4 * CLEN;
-                af[qq][0] = (int)apq[0];
-                af[qq][1] = (int)apq[1];
-                af[qq][2] = (int)apq[2];
-                af[qq][3] = (int)apq[3];
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t *apq = eb + q * 4 * CLEN;
+                af[q][0] = (int)apq[0];
+                af[q][1] = (int)apq[1];
+                af[q][2] = (int)apq[2];
+                af[q][3] = (int)apq[3];
             }
             const int Mb = (Jc - dl) & (NB - 1);
             const int sg = Jc < dl ? N : 0;
             bf = *reinterpret_cast<const v4i *>(dbase + (size_t)kb * 2 * N +
                                                 sg + Mb * 16);
         };
-        const int K = R * ND;                     // even: R is even
-        v16i C0 = {}, C1 = {};
-        v4i af[2][2], bf[2];
-        load(0, af[0], bf[0]);
+        const int K = RH * ND;
+        v16i Cq[4] = {};
+        v4i af0[4], af1[4], bf0, bf1;
+        auto mfma4 = [&](const v4i (&af)[4], const v4i &bf) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                Cq[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[q], bf, Cq[q],
+                                                              0, 0, 0);
+        };
+        load(0, af0, bf0);
 #pragma unroll 1
         for (int idx = 0; idx < K; idx += 2) {
-            load(idx + 1, af[1], bf[1]);
-            C0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[0][0], bf[0], C0,
-                                                       0, 0, 0);
-            C1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[0][1], bf[0], C1,
-                                                       0, 0, 0);
+            if (idx + 1 < K)
+                load(idx + 1, af1, bf1);
+            mfma4(af0, bf0);
+            if (idx + 1 >= K)
+                break;
             if (idx + 2 < K)
-                load(idx + 2, af[0], bf[0]);
-            C0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[1][0], bf[1], C0,
-                                                       0, 0, 0);
-            C1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[1][1], bf[1], C1,
-                                                       0, 0, 0);
+                load(idx + 2, af0, bf0);
+            mfma4(af1, bf1);
         }
-        // ---- fold the two limbs, add this wave's block offsets ----------
+        // ---- fold the four limbs, add this wave's block offsets ---------
         {
             uint32_t *pp = part + glc * AST + 33 * Jc;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 int row = 8 * (v >> 2) + 4 * hh + (v & 3);
-                uint32_t xv = (uint32_t)C0[v] + ((uint32_t)C1[v] << 8);
-                atomicAdd(&pp[row], xv << (8 * q0));
+                uint32_t xv = (uint32_t)Cq[0][v] + ((uint32_t)Cq[1][v] << 8) +
+                              ((uint32_t)Cq[2][v] << 16) +
+                              ((uint32_t)Cq[3][v] << 24);
+                atomicAdd(&pp[row], xv);
             }
         }
-        __syncthreads();   // partial complete; key windows free
+        lds_barrier();   // partial complete; key windows free
 
         // ---- publish the partial (tag = epoch * 1024 + step + 1) --------
         const unsigned long long tag =
@@ -758,11 +779,6 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                                __HIP_MEMORY_SCOPE_AGENT);
             *pp = 0u;
         }
-        if (i + 1 < n) {
-            stash();
-            if (i + 2 < n)
-                fetch(i + 2);
-        }
         // ---- gather the four partials of both components ----------------
         const unsigned long long *xr = xg + (size_t)(i & 1) * SPLIT_G * WORDS;
         unsigned long long wv[SPLIT_G][PW];
@@ -773,33 +789,44 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                 wv[mb][k] = __hip_atomic_load(&xr[mb * WORDS + tid + k * T],
                                               __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT);
+        // the key windows of step i + 1: read while the partials arrive
+        // (unconditionally, so the waits below count exactly; the last step
+        // re-reads its own windows and stores nothing)
+        fetch(min(i + 1, n - 1));
+        // every word is tested (no short cut), so no read is left in flight
+        auto all_tagged = [&]() {
+            unsigned long long diff = 0;
+#pragma unroll
+            for (int mb = 0; mb < SPLIT_G; ++mb)
+#pragma unroll
+                for (int k = 0; k < PW; ++k)
+                    diff |= (wv[mb][k] & 0xFFFFFFFF00000000ull) ^ tag;
+            return diff == 0;
+        };
         bool failed = false;
-        const unsigned long long t_start = wall_clock64();
-        for (int it = 1;; ++it) {
-            bool ok = true;
+        // the first test sits outside any loop, so it waits for the gather
+        // reads only (the key reads issued after them stay in flight)
+        if (!all_tagged()) {
+            const unsigned long long t_start = wall_clock64();
+            for (int it = 1;; ++it) {
+                if ((it & 15) == 0 &&
+                    (__hip_atomic_load(err, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                     wall_clock64() - t_start > SPLIT_WAIT_TICKS)) {
+                    __hip_atomic_store(err, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    failed = true;
+                    break;
+                }
 #pragma unroll
-            for (int mb = 0; mb < SPLIT_G; ++mb)
+                for (int mb = 0; mb < SPLIT_G; ++mb)
 #pragma unroll
-                for (int k = 0; k < PW; ++k)
-                    ok = ok && (wv[mb][k] & 0xFFFFFFFF00000000ull) == tag;
-            if (ok)
-                break;
-#pragma unroll
-            for (int mb = 0; mb < SPLIT_G; ++mb)
-#pragma unroll
-                for (int k = 0; k < PW; ++k)
-                    if ((wv[mb][k] & 0xFFFFFFFF00000000ull) != tag)
+                    for (int k = 0; k < PW; ++k)
                         wv[mb][k] = __hip_atomic_load(
                             &xr[mb * WORDS + tid + k * T], __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_AGENT);
-            if ((it & 15) == 0 &&
-                (__hip_atomic_load(err, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                 wall_clock64() - t_start > SPLIT_WAIT_TICKS)) {
-                __hip_atomic_store(err, 1u, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                failed = true;
-                break;
+                if (all_tagged())
+                    break;
             }
         }
         if (failed) {
@@ -815,6 +842,8 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                         (uint32_t)wv[c2][k] + (uint32_t)wv[c2 + 2][k];
             }
         }
+        if (i + 1 < n)
+            stash();
     }
     __syncthreads();
     if (s_stop || member != 0)

@@ -118,4 +118,7 @@ def test_batch_calls_reject_null_context():
     assert L.cggi_keyswitch_batch(None, None, None, 4, None) == cggi.E_PARAM
     assert L.cggi_eval_level(None, 1, None, 1, None, 1, None) == cggi.E_PARAM
     assert L.cggi_ctx_reserve(None, 4) == cggi.E_PARAM
+    assert L.cggi_ctx_latency_mode(None, 1) == cggi.E_PARAM
+    assert L.cggi_ctx_latency_groups(None, None) == cggi.E_PARAM
+    assert L.cggi_ctx_check(None) == cggi.E_PARAM
     assert L.cggi_ctx_destroy(None) == cggi.OK
