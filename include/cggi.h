@@ -204,22 +204,27 @@ int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
  * names splitting one gate over several SMs as the way to speed up narrow
  * circuit levels; here a narrow batch runs each column tile's blind
  * rotation (1024/N bootstraps) on four workgroups on four CUs, one per
- * (output component, pair of key limbs), which exchange their partial
- * products after every CMux step through device memory.  Results are
- * bit-identical to the one-workgroup kernel.  A cggi_bootstrap_batch or
- * cggi_eval_level call of the INT8 form uses it when it is on and the
- * call's B (2G for a level of G gates) needs at most *groups tiles, where
- * cggi_ctx_latency_groups reports the context's limit (every workgroup of
+ * block (input component, output component) of the external product, or,
+ * for up to twice as many tiles, on two (one per output component), which
+ * exchange their partial products after every CMux step through device
+ * memory.  Results are bit-identical to the one-workgroup kernel.  Every
+ * INT8 call picks its kernel from the batch size: latency mode with four,
+ * then two workgroups per tile while the tiles fit, then one workgroup per
+ * 1, 2 or 4 tiles.  cggi_bootstrap_batch decides on the host from B;
+ * cggi_eval_level, whose bootstrap count is known only on the device,
+ * launches every candidate up to the one that holds 2G bootstraps, and each
+ * runs only if the device count falls in its range.  cggi_ctx_latency_groups
+ * reports the most tiles a latency-mode launch takes (every workgroup of
  * such a launch is resident at once; 0 when latency mode is off or
  * unavailable: N = 2048, more than 8 digit polynomials, or LDS).  It is on
  * by default; cggi_ctx_latency_mode(ctx, 0) turns it off, e.g. when other
- * streams keep the GPU's CUs busy, since the four workgroups of a tile wait
- * for each other.  Each wait is bounded (1 s): on a time-out the kernel
- * sets an error word in the context and stops, and every later latency-mode
- * launch on the context does nothing until cggi_ctx_check, which waits for
- * the device, returns CGGI_E_TIMEOUT if the word was set (clearing it and
- * the exchange buffers), else CGGI_OK.  Latency-mode launches on one
- * context must not run concurrently (they share its exchange buffers). */
+ * streams keep the GPU's CUs busy, since the workgroups of a tile wait for
+ * each other.  Each wait is bounded (1 s): on a time-out the kernel sets an
+ * error word in the context and stops, and every later latency-mode launch
+ * on the context does nothing until cggi_ctx_check, which waits for the
+ * device, returns CGGI_E_TIMEOUT if the word was set (clearing it and the
+ * exchange buffers), else CGGI_OK.  Latency-mode launches on one context
+ * must not run concurrently (they share its exchange buffers). */
 int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable);
 int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups);
 int cggi_ctx_check(cggi_ctx *ctx);

@@ -115,8 +115,10 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
-    (void)hipFree(c->x_buf);
-    (void)hipFree(c->x_epoch);
+    for (int v = 0; v < 2; ++v) {
+        (void)hipFree(c->x_buf[v]);
+        (void)hipFree(c->x_epoch[v]);
+    }
     (void)hipFree(c->x_err);
     (void)hipFree(c->ksk_i8);
     (void)hipFree(c->ws_small);
@@ -409,7 +411,10 @@ int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups)
 {
     if (!ctx || !groups)
         return set_error(CGGI_E_PARAM, "ctx or groups is NULL");
-    *groups = ctx->split_on ? ctx->split_groups : 0;
+    const int g = ctx->split_groups[0] > ctx->split_groups[1]
+                      ? ctx->split_groups[0]
+                      : ctx->split_groups[1];
+    *groups = ctx->split_on ? g : 0;
     return CGGI_OK;
 }
 

@@ -232,7 +232,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     const int8_t *__restrict__ key,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
-    int n, int beta, int l_rt, int S_rt)
+    int lo, int hi, int n, int beta, int l_rt, int S_rt)
 {
     using C = I8Cfg<N, T>;
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
@@ -252,9 +252,12 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPW * R * 2 * N);
     auto ap = [](int j) { return j + (j >> 5); };            // padded index
 
-    int count = B;
-    if (d_count)
-        count = min(count, *d_count);
+    // a launch issued next to others for a count read on the device runs
+    // only when lo < count <= hi
+    const int dc = d_count ? *d_count : B;
+    if (dc <= lo || dc > hi)
+        return;
+    const int count = min(B, dc);
     const int g0 = blockIdx.x * GPW;
     if (g0 >= count)
         return;
@@ -544,7 +547,6 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 // stops; later launches on the context do nothing until cggi_ctx_check
 // clears it.  The members of a group are placed on one XCD (blocks of one
 // group are congruent mod 8), which keeps the exchange in one L2.
-constexpr int SPLIT_G = 4;
 constexpr int SPLIT_THREADS = 512;
 constexpr int SPLIT_RMAX = 8;            // digit polynomials per step
 constexpr unsigned long long SPLIT_WAIT_TICKS = 100000000ull;   // 1 s
@@ -560,23 +562,30 @@ template <int N> struct SplitCfg {
     static constexpr int WORDS = GPT * N;   // partial words per member
 };
 
-template <int N>
+// G = 4 members per tile as above; G = 2 (for batches up to twice as
+// wide) gives member m = c' both input components.
+template <int N, int G>
 static size_t split_smem_bytes(int R, int n)
 {
     using C = SplitCfg<N>;
-    size_t b = (size_t)R * 8 * C::CLEN * 4          // key windows of a step
-               + (size_t)C::GPT * 3 * C::AST * 4    // accumulators + partial
-               + (size_t)C::GPT * (R / 2) * 2 * N;  // digit operands
+    const int RM = G == 4 ? R / 2 : R;               // digit rows per member
+    size_t b = (size_t)RM * 16 * C::CLEN * 4         // key windows of a step
+               + (size_t)C::GPT * 3 * C::AST * 4     // accumulators + partial
+               + (size_t)C::GPT * RM * 2 * N;        // digit operands
     return b + (((size_t)C::GPT * (n + 1) * 2 + 15) & ~(size_t)15);
 }
 
-template <int N, int L, int S>
+// Launches that read their bootstrap count from the device may be issued
+// for several kernels at once; each runs only when lo < count <= hi.
+template <int N, int L, int S, int G>
 __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int8_t *__restrict__ key, const uint32_t *__restrict__ in,
     const uint32_t *__restrict__ testv, uint32_t *__restrict__ out, int B,
-    const int32_t *__restrict__ d_count, unsigned long long *xb,
-    uint32_t *epoch, uint32_t *err, int n, int beta, int l_rt, int S_rt)
+    const int32_t *__restrict__ d_count, int lo, int hi,
+    unsigned long long *xb, uint32_t *epoch, uint32_t *err, int n, int beta,
+    int l_rt, int S_rt)
 {
+    static_assert(G == 4 || G == 2, "four or two members per tile");
     using C = SplitCfg<N>;
     constexpr int NB = C::NB, GPT = C::GPT, ND = C::ND, EW = C::EW;
     constexpr int CW = C::CW, CLEN = C::CLEN, AST = C::AST;
@@ -586,29 +595,32 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int SS = L ? S : S_rt;
     const int R = 2 * l * SS;
     const int RH = l * SS;                 // digit rows of one component
+    const int RM = G == 4 ? RH : R;        // digit rows of this member
 
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);  // [RH][4][4][CLEN]
-    uint32_t *acc = ecop + R * 8 * CLEN;                    // [GPT][2][AST]
+    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);  // [RM][4][4][CLEN]
+    uint32_t *acc = ecop + RM * 16 * CLEN;                  // [GPT][2][AST]
     uint32_t *part = acc + GPT * 2 * AST;                   // [GPT][AST]
     int8_t *dig = reinterpret_cast<int8_t *>(part + GPT * AST);
     uint16_t *ms =
-        reinterpret_cast<uint16_t *>(dig + (size_t)GPT * RH * 2 * N);
+        reinterpret_cast<uint16_t *>(dig + (size_t)GPT * RM * 2 * N);
     __shared__ int s_stop;
     __shared__ uint32_t s_ep;
     auto ap = [](int j) { return j + (j >> 5); };
 
-    // block -> (group, member): the four members of a group share b mod 8
+    // block -> (group, member): the members of a group share b mod 8
     const int x8 = blockIdx.x & 7, q8 = blockIdx.x >> 3;
-    const int member = q8 & (SPLIT_G - 1);
-    const int grp = (q8 / SPLIT_G) * 8 + x8;
-    int count = B;
-    if (d_count)
-        count = min(count, *d_count);
+    const int member = q8 % G;
+    const int grp = (q8 / G) * 8 + x8;
+    const int dc = d_count ? *d_count : B;
+    if (dc <= lo || dc > hi)
+        return;
+    const int count = min(B, dc);
     const int g0 = grp * GPT;
     if (g0 >= count)
         return;
-    const int cp = member & 1, ch = member >> 1;
+    const int cp = G == 4 ? member & 1 : member;
+    const int ch = G == 4 ? member >> 1 : 0;    // first input component
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 
@@ -651,9 +663,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     // step i + 1's are read while step i's partials are exchanged (the two
     // latencies overlap) and then written to LDS in four byte-shifted
     // copies; no read stays in flight from one step into the next
-    constexpr int RMAX = L ? 2 * L * S : SPLIT_RMAX;
-    constexpr int PER_T = (RMAX * 2 * CW + T - 1) / T;
-    const int items = RH * 4 * CW;
+    constexpr int RMAX = (L ? 2 * L * S : SPLIT_RMAX) / (G == 4 ? 2 : 1);
+    constexpr int PER_T = (RMAX * 4 * CW + T - 1) / T;
+    const int items = RM * 4 * CW;
     uint32_t pre_lo[PER_T], pre_hi[PER_T];
     auto fetch = [&](int i) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
@@ -700,20 +712,25 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         dig_off += (1u << (beta - 1)) << (32 - p * beta);
     const uint32_t bmask = (1u << beta) - 1u;
     const int32_t bhalf = 1 << (beta - 1);
-    unsigned long long *xg = xb + (size_t)grp * 2 * SPLIT_G * WORDS;
-    const int8_t *dbase = dig + (size_t)glc * RH * 2 * N + hh * (NB * 16);
+    unsigned long long *xg = xb + (size_t)grp * 2 * G * WORDS;
+    const int8_t *dbase = dig + (size_t)glc * RM * 2 * N + hh * (NB * 16);
     constexpr int PW = WORDS / T;                 // words per thread
 
     for (int i = 0; i < n; ++i) {
         lds_barrier();   // ACC and this step's key windows complete
         if (s_stop)
             break;
-        decompose_acc<N, L, S, GPT, T, 1>(acc, dig, ms, i, n, l, SS, RH,
-                                          beta, dig_off, bmask, bhalf, tid,
-                                          ch);
+        if constexpr (G == 4)
+            decompose_acc<N, L, S, GPT, T, 1>(acc, dig, ms, i, n, l, SS, RH,
+                                              beta, dig_off, bmask, bhalf,
+                                              tid, ch);
+        else
+            decompose_acc<N, L, S, GPT, T, 2>(acc, dig, ms, i, n, l, SS, R,
+                                              beta, dig_off, bmask, bhalf,
+                                              tid);
         lds_barrier();
 
-        // ---- K loop over (digit row of component ch, block offset) ------
+        // ---- K loop over (digit row of the member, block offset) --------
         auto load = [&](int idx, v4i (&af)[4], v4i &bf) {
             const int kb = idx / ND, dl = dl0 + idx % ND;
             const uint32_t *eb = ecop + kb * 16 * CLEN + a_lane + 8 * dl;
@@ -730,7 +747,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
             bf = *reinterpret_cast<const v4i *>(dbase + (size_t)kb * 2 * N +
                                                 sg + Mb * 16);
         };
-        const int K = RH * ND;
+        const int K = RM * ND;
         v16i Cq[4] = {};
         v4i af0[4], af1[4], bf0, bf1;
         auto mfma4 = [&](const v4i (&af)[4], const v4i &bf) {
@@ -769,7 +786,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         const unsigned long long tag =
             (unsigned long long)(ep * 1024u + (uint32_t)i + 1u) << 32;
         unsigned long long *xw =
-            xg + ((size_t)(i & 1) * SPLIT_G + member) * WORDS;
+            xg + ((size_t)(i & 1) * G + member) * WORDS;
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
             const int m = tid + k * T;
@@ -779,11 +796,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                                __HIP_MEMORY_SCOPE_AGENT);
             *pp = 0u;
         }
-        // ---- gather the four partials of both components ----------------
-        const unsigned long long *xr = xg + (size_t)(i & 1) * SPLIT_G * WORDS;
-        unsigned long long wv[SPLIT_G][PW];
+        // ---- gather the partials of every member ------------------------
+        const unsigned long long *xr = xg + (size_t)(i & 1) * G * WORDS;
+        unsigned long long wv[G][PW];
 #pragma unroll
-        for (int mb = 0; mb < SPLIT_G; ++mb)
+        for (int mb = 0; mb < G; ++mb)
 #pragma unroll
             for (int k = 0; k < PW; ++k)
                 wv[mb][k] = __hip_atomic_load(&xr[mb * WORDS + tid + k * T],
@@ -797,7 +814,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         auto all_tagged = [&]() {
             unsigned long long diff = 0;
 #pragma unroll
-            for (int mb = 0; mb < SPLIT_G; ++mb)
+            for (int mb = 0; mb < G; ++mb)
 #pragma unroll
                 for (int k = 0; k < PW; ++k)
                     diff |= (wv[mb][k] & 0xFFFFFFFF00000000ull) ^ tag;
@@ -819,7 +836,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                     break;
                 }
 #pragma unroll
-                for (int mb = 0; mb < SPLIT_G; ++mb)
+                for (int mb = 0; mb < G; ++mb)
 #pragma unroll
                     for (int k = 0; k < PW; ++k)
                         wv[mb][k] = __hip_atomic_load(
@@ -837,9 +854,13 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                 const int m = tid + k * T;
                 const int gl = m / N, j = m - gl * N;
 #pragma unroll
-                for (int c2 = 0; c2 < 2; ++c2)
-                    acc[(gl * 2 + c2) * AST + ap(j)] +=
-                        (uint32_t)wv[c2][k] + (uint32_t)wv[c2 + 2][k];
+                for (int c2 = 0; c2 < 2; ++c2) {
+                    // the members with output component c2
+                    uint32_t add = (uint32_t)wv[c2][k];
+                    if constexpr (G == 4)
+                        add += (uint32_t)wv[c2 + 2][k];
+                    acc[(gl * 2 + c2) * AST + ap(j)] += add;
+                }
             }
         }
         if (i + 1 < n)
@@ -886,35 +907,50 @@ size_t int8_smem_bytes(int N, int R, int n)
 // Latency mode set-up for one kernel instantiation: the largest number of
 // tile groups whose workgroups are all resident at once (so the members'
 // waits on each other always end), and the exchange buffers for them.
-template <int N, int L, int S>
-static int split_setup_t(Ctx *c, hipStream_t s)
+// Variant v = 0 has four members per tile, v = 1 two; each has its own
+// buffers and epochs (their word layouts differ).
+template <int N, int L, int S, int G>
+static int split_setup_g(Ctx *c, int v, hipStream_t s)
 {
     const Shape &sh = c->sh;
-    const size_t smem = split_smem_bytes<N>(sh.R, sh.n);
+    const size_t smem = split_smem_bytes<N, G>(sh.R, sh.n);
     // (the kernel also holds 8 bytes of static LDS)
     if (sh.R > SPLIT_RMAX || smem + 64 > 160 * 1024)
-        return CGGI_OK;                       // latency mode unavailable
+        return CGGI_OK;                       // this variant unavailable
     const void *fn =
-        reinterpret_cast<const void *>(&k_bootstrap_int8_split<N, L, S>);
+        reinterpret_cast<const void *>(&k_bootstrap_int8_split<N, L, S, G>);
     CGGI_HIP_TRY(hipFuncSetAttribute(
         fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
     int occ = 0;
     CGGI_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &occ, fn, SPLIT_THREADS, smem));
-    const int groups = c->cus * occ / SPLIT_G;
+    const int groups = c->cus * occ / G;
     if (groups < 1)
         return CGGI_OK;
-    const size_t xwords = (size_t)groups * 2 * SPLIT_G * SplitCfg<N>::WORDS;
-    if (hipMalloc(&c->x_buf, xwords * 8) != hipSuccess ||
-        hipMalloc(&c->x_epoch, (size_t)groups * 4) != hipSuccess ||
-        hipMalloc(&c->x_err, 4) != hipSuccess)
+    const size_t xwords = (size_t)groups * 2 * G * SplitCfg<N>::WORDS;
+    if (hipMalloc(&c->x_buf[v], xwords * 8) != hipSuccess ||
+        hipMalloc(&c->x_epoch[v], (size_t)groups * 4) != hipSuccess)
         return set_error(CGGI_E_NOMEM, "hipMalloc of the latency-mode "
                                        "exchange buffers failed");
-    CGGI_HIP_TRY(hipMemsetAsync(c->x_buf, 0, xwords * 8, s));
-    CGGI_HIP_TRY(hipMemsetAsync(c->x_epoch, 0, (size_t)groups * 4, s));
+    CGGI_HIP_TRY(hipMemsetAsync(c->x_buf[v], 0, xwords * 8, s));
+    CGGI_HIP_TRY(hipMemsetAsync(c->x_epoch[v], 0, (size_t)groups * 4, s));
+    c->x_words[v] = xwords;
+    c->split_groups[v] = groups;
+    return CGGI_OK;
+}
+
+template <int N, int L, int S>
+static int split_setup_t(Ctx *c, hipStream_t s)
+{
+    int rc = split_setup_g<N, L, S, 4>(c, 0, s);
+    if (!rc)
+        rc = split_setup_g<N, L, S, 2>(c, 1, s);
+    if (rc || (!c->split_groups[0] && !c->split_groups[1]))
+        return rc;
+    if (hipMalloc(&c->x_err, 4) != hipSuccess)
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the latency-mode "
+                                       "error word failed");
     CGGI_HIP_TRY(hipMemsetAsync(c->x_err, 0, 4, s));
-    c->x_words = xwords;
-    c->split_groups = groups;
     return CGGI_OK;
 }
 
@@ -935,10 +971,15 @@ static int split_setup(Ctx *c, hipStream_t s)
 
 int int8_split_reset(Ctx *c)
 {
-    if (!c->x_buf)
+    if (!c->x_err)
         return CGGI_OK;
-    CGGI_HIP_TRY(hipMemset(c->x_buf, 0, c->x_words * 8));
-    CGGI_HIP_TRY(hipMemset(c->x_epoch, 0, (size_t)c->split_groups * 4));
+    for (int v = 0; v < 2; ++v) {
+        if (!c->x_buf[v])
+            continue;
+        CGGI_HIP_TRY(hipMemset(c->x_buf[v], 0, c->x_words[v] * 8));
+        CGGI_HIP_TRY(
+            hipMemset(c->x_epoch[v], 0, (size_t)c->split_groups[v] * 4));
+    }
     CGGI_HIP_TRY(hipMemset(c->x_err, 0, 4));
     CGGI_HIP_TRY(hipDeviceSynchronize());
     return CGGI_OK;
@@ -976,7 +1017,8 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
 template <int N, int L, int S, int T>
 static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
                             const uint32_t *testv, uint32_t *out, int B,
-                            const int32_t *d_count, hipStream_t s)
+                            const int32_t *d_count, int lo, int hi,
+                            hipStream_t s)
 {
     using C = I8Cfg<N, T>;
     const Shape &sh = c->sh;
@@ -991,49 +1033,103 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8<N, L, S, T>), dim3(grid),
                        dim3(C::THREADS), smem, s, c->bsk_i8, in,
-                       testv, out, B, d_count, sh.n, sh.beta, sh.l, sh.S);
+                       testv, out, B, d_count, lo, hi, sh.n, sh.beta, sh.l,
+                       sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
 }
 
-template <int N, int L, int S>
+template <int N, int L, int S, int G>
 static int launch_split(const Ctx *c, const uint32_t *in,
                         const uint32_t *testv, uint32_t *out, int B,
-                        const int32_t *d_count, hipStream_t s)
+                        const int32_t *d_count, int lo, int hi, hipStream_t s)
 {
     const Shape &sh = c->sh;
+    const int v = G == 4 ? 0 : 1;
     const int groups = (B + SplitCfg<N>::GPT - 1) / SplitCfg<N>::GPT;
-    const int grid = (groups + 7) / 8 * 8 * SPLIT_G;
-    hipLaunchKernelGGL((k_bootstrap_int8_split<N, L, S>), dim3(grid),
-                       dim3(SPLIT_THREADS), split_smem_bytes<N>(sh.R, sh.n),
-                       s, c->bsk_i8, in, testv, out, B, d_count, c->x_buf,
-                       c->x_epoch, c->x_err, sh.n, sh.beta, sh.l, sh.S);
+    const int grid = (groups + 7) / 8 * 8 * G;
+    hipLaunchKernelGGL((k_bootstrap_int8_split<N, L, S, G>), dim3(grid),
+                       dim3(SPLIT_THREADS),
+                       (split_smem_bytes<N, G>(sh.R, sh.n)), s, c->bsk_i8, in,
+                       testv, out, B, d_count, lo, hi, c->x_buf[v],
+                       c->x_epoch[v], c->x_err, sh.n, sh.beta, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
 }
 
-// Batches of at most split_groups column tiles (bounded by B, the most the
-// launch can hold) run in latency mode when it is on; otherwise the column
-// tiles per workgroup are the fewest that still fit the batch into one wave
-// of workgroups over the CUs.
+// Kernel choice by batch size, in increasing capacity (bootstraps): latency
+// mode with four, then two workgroups per column tile (when on), then one
+// workgroup per 1, 2 or 4 column tiles (the fewest tiles per workgroup that
+// still fit the batch into one wave of workgroups over the CUs).  A count
+// known on the host takes the first option that holds it.  A count read on
+// the device (a level's bootstraps) is bounded by B only, so every option up
+// to the first that holds B is launched, each for the counts in its own
+// range (lo, hi]; the others exit at once.
 template <int N, int L, int S>
 static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
                             const uint32_t *testv, uint32_t *out, int B,
                             const int32_t *d_count, hipStream_t s)
 {
+    struct Opt {
+        int kind;   // 0, 1: latency mode G = 4, 2; 2, 3, 4: T = 1, 2, 4
+        long cap;
+    };
+    Opt opts[5];
+    int no = 0;
     if constexpr (N <= 1024) {
-        if (c->split_on && c->split_groups > 0 &&
-            (B + SplitCfg<N>::GPT - 1) / SplitCfg<N>::GPT <= c->split_groups)
-            return launch_split<N, L, S>(c, in, testv, out, B, d_count, s);
-        const long tiles = (B + I8Cfg<N>::GPT - 1) / I8Cfg<N>::GPT;
-        if (tiles <= c->cus)
-            return launch_bs_int8_t<N, L, S, 1>(c, in, testv, out, B, d_count,
-                                                s);
-        if (tiles <= 2L * c->cus)
-            return launch_bs_int8_t<N, L, S, 2>(c, in, testv, out, B, d_count,
-                                                s);
+        constexpr long gpt = SplitCfg<N>::GPT;
+        if (c->split_on) {
+            if (c->split_groups[0] > 0)
+                opts[no++] = {0, c->split_groups[0] * gpt};
+            if (c->split_groups[1] > c->split_groups[0])
+                opts[no++] = {1, c->split_groups[1] * gpt};
+        }
+        opts[no++] = {2, (long)c->cus * I8Cfg<N>::GPT};
+        opts[no++] = {3, 2L * c->cus * I8Cfg<N>::GPT};
     }
-    return launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, B, d_count, s);
+    opts[no++] = {4, 1L << 40};
+    long lo = 0;
+    for (int k = 0; k < no; ++k) {
+        const long cap = opts[k].cap;
+        const bool last = B <= cap;
+        if (!d_count && !last) {
+            lo = cap;
+            continue;
+        }
+        const int Bk = (int)(B < cap ? B : cap);
+        const int a = d_count ? (int)lo : 0;
+        const int b = d_count && !last ? (int)cap : INT32_MAX;
+        int rc;
+        switch (opts[k].kind) {
+        case 0:
+            if constexpr (N <= 1024)
+                rc = launch_split<N, L, S, 4>(c, in, testv, out, Bk, d_count,
+                                              a, b, s);
+            break;
+        case 1:
+            if constexpr (N <= 1024)
+                rc = launch_split<N, L, S, 2>(c, in, testv, out, Bk, d_count,
+                                              a, b, s);
+            break;
+        case 2:
+            if constexpr (N <= 1024)
+                rc = launch_bs_int8_t<N, L, S, 1>(c, in, testv, out, Bk,
+                                                  d_count, a, b, s);
+            break;
+        case 3:
+            if constexpr (N <= 1024)
+                rc = launch_bs_int8_t<N, L, S, 2>(c, in, testv, out, Bk,
+                                                  d_count, a, b, s);
+            break;
+        default:
+            rc = launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, Bk, d_count,
+                                              a, b, s);
+        }
+        if (rc || last)
+            return rc;
+        lo = cap;
+    }
+    return CGGI_OK;
 }
 
 template <int N>

@@ -38,12 +38,13 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
-    // INT8 latency mode (one tile over four workgroups, N <= 1024)
+    // INT8 latency mode (one tile over G = 4 or 2 workgroups, N <= 1024);
+    // index 0: G = 4, index 1: G = 2
     bool split_on = true;         // cggi_ctx_latency_mode
-    int split_groups = 0;         // most tile groups per launch (0: off)
-    unsigned long long *x_buf = nullptr; // [groups][2][4][1024] tagged words
-    size_t x_words = 0;
-    uint32_t *x_epoch = nullptr;  // [groups] launch epoch per group slot
+    int split_groups[2] = {0, 0}; // most tile groups per launch (0: none)
+    unsigned long long *x_buf[2] = {nullptr, nullptr}; // [groups][2][G][1024]
+    size_t x_words[2] = {0, 0};
+    uint32_t *x_epoch[2] = {nullptr, nullptr}; // [groups] launch epochs
     uint32_t *x_err = nullptr;    // [1] set when a member's wait timed out
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks

@@ -1,9 +1,10 @@
 """Latency mode of the int8 form: a narrow batch runs each column tile's
-blind rotation on four workgroups that exchange partial products after
-every CMux step.  Bit-exact against the oracle and the NTT form, identical
-to the one-workgroup kernel, at every N <= 1024 and digit shape (specialised
-and generic builds), over partial tiles, repeated launches (launch epochs)
-and HIP-graph replays of a whole narrow circuit."""
+blind rotation on four (or, for up to twice as many tiles, two) workgroups
+that exchange partial products after every CMux step.  Bit-exact against
+the oracle and the NTT form, identical to the one-workgroup kernel, at every
+N <= 1024 and digit shape (specialised and generic builds), over partial
+tiles, repeated launches (launch epochs), and HIP-graph replays of a whole
+circuit whose levels pick every kernel from their device-side counts."""
 import concurrent.futures as cf
 import dataclasses
 import os
@@ -41,8 +42,8 @@ def make_ctx(p, seed):
 CASES = [
     # (parameter set, batch sizes): N = 1024 (l=3, S=1 build), N = 256 with
     # Bg = 2^8 (two sub-digits, the l=2 S=2 build, four bootstraps per tile)
-    (params.DEFAULT, (1, 3, 64)),
-    (params.TOY, (1, 5, 255)),
+    (params.DEFAULT, (1, 3, 64, 100, 128)),
+    (params.TOY, (1, 5, 255, 300)),
     (dataclasses.replace(params.DEFAULT, name="n512_N512", n=512, N=512),
      (2, 9)),
     # generic build (digit loops with run-time bounds): l = 2 levels of 2^7
@@ -103,10 +104,11 @@ def test_latency_mode_limits():
 
 def test_latency_mode_repeated_launches_and_graph():
     """Back-to-back launches of varying width advance the per-group epochs;
-    a narrow circuit (32-bit prefix adder: its first level of 64 gates takes
-    the one-workgroup kernel, the six levels of 15 to 32 gates latency mode)
-    captured as one HIP graph and replayed three times, with eager work
-    between the replays, equals the eager run every time."""
+    a 32-bit Dadda multiplier (levels of 14 to 1,024 gates, so its levels
+    take latency mode with four and two workgroups per tile and one
+    workgroup per 1, 2 or 4 tiles, chosen on the device from each level's
+    bootstrap count) captured as one HIP graph and replayed three times,
+    with eager work between the replays, equals the eager run every time."""
     import torch
     from paper_2306_11006_amd import cggi
     from paper_2306_11006_amd.circuit import LevelledCircuit
@@ -121,10 +123,9 @@ def test_latency_mode_repeated_launches_and_graph():
         assert np.array_equal(got, ref[:B]), B
     ctx.check()
 
-    nl, io = arith.adder(32, "prefix")
+    nl, io = arith.multiplier(32, "tree")
     circ = LevelledCircuit(nl.array(), nl.n_wires)
-    narrow = [w for w in circ.widths if 2 * w <= groups]
-    assert len(narrow) == circ.n_levels - 1, (circ.widths, groups)
+    assert min(circ.widths) * 2 <= groups // 2 and max(circ.widths) > 512
     wires = np.zeros((nl.n_wires, p.n + 1), dtype=np.uint32)
     ins = list(io["a"]) + list(io["b"])
     wires[ins] = inputs.uniform_lwe(p, 7402, len(ins))
