@@ -214,7 +214,7 @@ def main():
                 "frac": round(achieved / PEAK_INT8_TOPS, 4),
                 "traffic": stored_traffic() if G == 1024 else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
-                "kernel": "k_bootstrap_int8<1024>",
+                "kernel": "k_bootstrap_int8<1024, 3, 1, 4>",
                 "per_launch": f"{G} bootstraps x {int8_ops_per_bootstrap(p):.4g}"
                               " int8 ops"}
     else:
