@@ -229,6 +229,39 @@ int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable);
 int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups);
 int cggi_ctx_check(cggi_ctx *ctx);
 
+/* INT8 kernel plan (autotuning).  The INT8 form has five kernels for a
+ * batch: CGGI_K_SPLIT4 and CGGI_K_SPLIT2 (latency mode, four or two
+ * workgroups per column tile; N <= 1024), CGGI_K_TILES1, CGGI_K_TILES2
+ * (one workgroup per one or two column tiles; N <= 1024) and CGGI_K_TILES4
+ * (four tiles, or one bootstrap per workgroup at N = 2048).  A plan is a
+ * list of entries (kinds[k], caps[k]) with strictly increasing caps: entry
+ * k takes the batches of caps[k-1] + 1 .. caps[k] bootstraps (caps[-1] = 0);
+ * the last cap must be at least 2^24 (every batch); a latency-mode entry's
+ * cap may not exceed that kind's limit (cggi_ctx_int8_limits: the most
+ * bootstraps one launch of each kind may take, 0 if the kind is
+ * unavailable; latency-mode limits keep every workgroup resident).  All
+ * kinds give bit-identical results; the plan only changes speed.  count = 0
+ * restores the built-in plan (latency mode with four, then two workgroups
+ * while the tiles fit, then 1, 2 or 4 tiles per workgroup by batch width;
+ * see cggi_ctx_latency_mode).  While latency mode is off its entries are
+ * skipped and their batches go to the next entry.  cggi_ctx_int8_plan_get
+ * writes the plan in force (at most max entries; count = entries).  Host
+ * state only: affects calls made afterwards.  Errors: CGGI_E_PARAM for a NULL
+ * ctx or an invalid plan (nothing changes), CGGI_E_UNSUPPORTED without the
+ * INT8 form, CGGI_E_SHAPE when max is too small. */
+enum {
+    CGGI_K_SPLIT4 = 0,
+    CGGI_K_SPLIT2 = 1,
+    CGGI_K_TILES1 = 2,
+    CGGI_K_TILES2 = 3,
+    CGGI_K_TILES4 = 4
+};
+int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
+                       const int32_t *caps, int32_t count);
+int cggi_ctx_int8_plan_get(const cggi_ctx *ctx, int32_t *kinds,
+                           int32_t *caps, int32_t max, int32_t *count);
+int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits /* [5] */);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);
 

@@ -29,7 +29,12 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_eval_level", "cggi_levelize", "cggi_ctx_profile",
            "cggi_ctx_profile_read", "cggi_measure_int8_mfma",
            "cggi_ctx_latency_mode", "cggi_ctx_latency_groups",
-           "cggi_ctx_check", "cggi_last_error"]
+           "cggi_ctx_check", "cggi_ctx_int8_plan", "cggi_ctx_int8_plan_get",
+           "cggi_ctx_int8_limits", "cggi_last_error"]
+
+# INT8 kernel kinds of a plan (cggi_ctx_int8_plan), in the header's order
+KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4")
+INT32_MAX = 2**31 - 1
 
 
 class CggiError(RuntimeError):
@@ -74,6 +79,9 @@ def lib():
         L.cggi_ctx_latency_mode.argtypes = [vp, i32]
         L.cggi_ctx_latency_groups.argtypes = [vp, ip]
         L.cggi_ctx_check.argtypes = [vp]
+        L.cggi_ctx_int8_plan.argtypes = [vp, ip, ip, i32]
+        L.cggi_ctx_int8_plan_get.argtypes = [vp, ip, ip, i32, ip]
+        L.cggi_ctx_int8_limits.argtypes = [vp, ip]
         L.cggi_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -152,6 +160,7 @@ class Context:
 
     def __init__(self, params, bsk, ksk, forms=("ntt", "int8"), stream=None):
         self.params = params
+        self.forms = tuple(forms)
         self._ksk = ksk          # the library keeps a pointer to it
         mask = 0
         for f in forms:
@@ -207,6 +216,34 @@ class Context:
         g = ctypes.c_int32()
         _check(lib().cggi_ctx_latency_groups(self._h, ctypes.byref(g)))
         return g.value
+
+    def int8_plan(self, plan=None):
+        """Set the INT8 kernel plan: a list of (kind, cap) with kind a name
+        of KINDS (or its index) and strictly increasing caps, the last at
+        least 2^24; None or [] restores the built-in plan."""
+        plan = list(plan or [])
+        n = len(plan)
+        kinds = (ctypes.c_int32 * max(n, 1))(
+            *[KINDS.index(k) if isinstance(k, str) else int(k)
+              for k, _ in plan])
+        caps = (ctypes.c_int32 * max(n, 1))(*[int(c) for _, c in plan])
+        _check(lib().cggi_ctx_int8_plan(self._h, kinds, caps, n))
+
+    def int8_plan_get(self):
+        """The INT8 kernel plan in force, as [(kind name, cap)]."""
+        kinds = (ctypes.c_int32 * 8)()
+        caps = (ctypes.c_int32 * 8)()
+        n = ctypes.c_int32()
+        _check(lib().cggi_ctx_int8_plan_get(self._h, kinds, caps, 8,
+                                            ctypes.byref(n)))
+        return [(KINDS[kinds[k]], caps[k]) for k in range(n.value)]
+
+    def int8_limits(self):
+        """{kind name: most bootstraps one launch of it may take} (0 when
+        the kind is unavailable)."""
+        lim = (ctypes.c_int32 * 5)()
+        _check(lib().cggi_ctx_int8_limits(self._h, lim))
+        return {KINDS[k]: lim[k] for k in range(5)}
 
     def check(self):
         """Wait for the device; raise CggiError(E_TIMEOUT) if a

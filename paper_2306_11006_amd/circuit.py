@@ -24,23 +24,37 @@ class LevelledCircuit:
                        for i in range(len(start) - 1)]
         self.d_levels = [cggi.to_device(lv, device) for lv in self.levels]
         self.widths = [len(lv) for lv in self.levels]
+        self.level_bootstraps = [self._bootstraps(lv) for lv in self.levels]
 
     @property
     def n_levels(self):
         return len(self.levels)
 
-    def bootstraps(self):
-        ops = self.gates[:, 0]
+    @staticmethod
+    def _bootstraps(gates):
+        ops = gates[:, 0]
         return int(np.isin(ops, (0, 1, 2, 3, 9, 10)).sum() +
                    2 * (ops == 4).sum())
 
-    def run(self, ctx, form, wires, stream=None):
+    def bootstraps(self):
+        return self._bootstraps(self.gates)
+
+    def forms_for(self, form, table=None):
+        """The form of each level: `form` itself, or for form == "auto" the
+        faster one at the level's bootstrap count in an autotuner table
+        (paper_2306_11006_amd.tune)."""
+        if form != "auto":
+            return [form] * self.n_levels
+        from .tune import best_form
+        return [best_form(table or {}, b) for b in self.level_bootstraps]
+
+    def run(self, ctx, form, wires, stream=None, table=None):
         ctx.reserve(max(self.widths) if self.widths else 0)
-        for lv in self.d_levels:
-            ctx.eval_level(form, lv, wires, stream=stream)
+        for lv, f in zip(self.d_levels, self.forms_for(form, table)):
+            ctx.eval_level(f, lv, wires, stream=stream)
         return wires
 
-    def capture(self, ctx, form, wires):
+    def capture(self, ctx, form, wires, table=None):
         """Record all levels into one graph; replay with graph.replay().
         The workspace is reserved first, so nothing is allocated inside."""
         ctx.reserve(max(self.widths) if self.widths else 0)
@@ -49,6 +63,6 @@ class LevelledCircuit:
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph, stream=side):
-            for lv in self.d_levels:
-                ctx.eval_level(form, lv, wires)
+            for lv, f in zip(self.d_levels, self.forms_for(form, table)):
+                ctx.eval_level(f, lv, wires)
         return graph

@@ -418,6 +418,78 @@ int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups)
     return CGGI_OK;
 }
 
+int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
+                       const int32_t *caps, int32_t count)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (!(ctx->forms & CGGI_FORM_INT8))
+        return set_error(CGGI_E_UNSUPPORTED, "INT8 form not built into the "
+                                             "context");
+    if (count == 0) {
+        ctx->plan_n = 0;
+        return CGGI_OK;
+    }
+    if (count < 0 || count > 8 || !kinds || !caps)
+        return set_error(CGGI_E_PARAM, "count must be in [0, 8] and kinds, "
+                                       "caps non-NULL");
+    for (int k = 0; k < count; ++k) {
+        if (kinds[k] < 0 || kinds[k] > 4 || ctx->kind_limit[kinds[k]] <= 0)
+            return set_error(CGGI_E_PARAM, "plan entry " + std::to_string(k) +
+                                               ": kernel kind unavailable");
+        if (caps[k] < 1 || (k > 0 && caps[k] <= caps[k - 1]))
+            return set_error(CGGI_E_PARAM, "plan caps must be positive and "
+                                           "strictly increasing");
+        if ((int64_t)caps[k] > ctx->kind_limit[kinds[k]])
+            return set_error(CGGI_E_PARAM,
+                             "plan entry " + std::to_string(k) +
+                                 ": cap exceeds the kind's limit (" +
+                                 std::to_string(ctx->kind_limit[kinds[k]]) +
+                                 " bootstraps)");
+    }
+    if (caps[count - 1] < (1 << 24))
+        return set_error(CGGI_E_PARAM, "the last plan entry must hold every "
+                                       "batch (cap >= 2^24)");
+    for (int k = 0; k < count; ++k) {
+        ctx->plan_kind[k] = kinds[k];
+        ctx->plan_cap[k] = caps[k];
+    }
+    ctx->plan_n = count;
+    return CGGI_OK;
+}
+
+int cggi_ctx_int8_plan_get(const cggi_ctx *ctx, int32_t *kinds,
+                           int32_t *caps, int32_t max, int32_t *count)
+{
+    if (!ctx || !count || max < 0 || (max > 0 && (!kinds || !caps)))
+        return set_error(CGGI_E_PARAM, "ctx or count NULL, or arrays NULL");
+    if (!(ctx->forms & CGGI_FORM_INT8))
+        return set_error(CGGI_E_UNSUPPORTED, "INT8 form not built into the "
+                                             "context");
+    int32_t k0[8], c0[8];
+    const int n = int8_active_plan(ctx, k0, c0);
+    if (n > max)
+        return set_error(CGGI_E_SHAPE, "max is smaller than the plan (" +
+                                           std::to_string(n) + " entries)");
+    for (int k = 0; k < n; ++k) {
+        kinds[k] = k0[k];
+        caps[k] = c0[k];
+    }
+    *count = n;
+    return CGGI_OK;
+}
+
+int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits)
+{
+    if (!ctx || !limits)
+        return set_error(CGGI_E_PARAM, "ctx or limits is NULL");
+    for (int k = 0; k < 5; ++k)
+        limits[k] = ctx->kind_limit[k] > INT32_MAX
+                        ? INT32_MAX
+                        : (int32_t)ctx->kind_limit[k];
+    return CGGI_OK;
+}
+
 int cggi_ctx_check(cggi_ctx *ctx)
 {
     if (!ctx)

@@ -1000,7 +1000,59 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
                        c->bsk_i8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
-    return split_setup<N>(c, s);
+    int rc = split_setup<N>(c, s);
+    if (rc)
+        return rc;
+    constexpr int64_t ANY = (int64_t)1 << 40;
+    constexpr int64_t gpt = N <= 1024 ? 1024 / N : 1;
+    c->kind_limit[0] = (int64_t)c->split_groups[0] * gpt;
+    c->kind_limit[1] = (int64_t)c->split_groups[1] * gpt;
+    c->kind_limit[2] = N <= 1024 ? ANY : 0;
+    c->kind_limit[3] = N <= 1024 ? ANY : 0;
+    c->kind_limit[4] = ANY;
+    return CGGI_OK;
+}
+
+int int8_active_plan(const Ctx *c, int32_t *kind, int32_t *cap)
+{
+    int32_t k0[8], c0[8];
+    int n0 = 0;
+    if (c->plan_n > 0) {
+        for (int k = 0; k < c->plan_n; ++k) {
+            k0[k] = c->plan_kind[k];
+            c0[k] = c->plan_cap[k];
+        }
+        n0 = c->plan_n;
+    } else {
+        // built-in: latency mode with four, then two workgroups per tile
+        // while the tiles fit; then the fewest tiles per workgroup that
+        // still fit the batch into one wave of workgroups over the CUs
+        const int64_t gpt = c->sh.N <= 1024 ? 1024 / c->sh.N : 1;
+        if (c->kind_limit[0] > 0) {
+            k0[n0] = 0;
+            c0[n0++] = (int32_t)c->kind_limit[0];
+        }
+        if (c->kind_limit[1] > c->kind_limit[0]) {
+            k0[n0] = 1;
+            c0[n0++] = (int32_t)c->kind_limit[1];
+        }
+        if (c->kind_limit[2] > 0) {
+            k0[n0] = 2;
+            c0[n0++] = (int32_t)(c->cus * gpt);
+            k0[n0] = 3;
+            c0[n0++] = (int32_t)(2 * c->cus * gpt);
+        }
+        k0[n0] = 4;
+        c0[n0++] = INT32_MAX;
+    }
+    int n = 0;
+    for (int k = 0; k < n0; ++k) {
+        if (!c->split_on && k0[k] <= 1)
+            continue;          // its batches go to the next entry
+        kind[n] = k0[k];
+        cap[n++] = c0[k];
+    }
+    return n;
 }
 
 int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
@@ -1057,77 +1109,60 @@ static int launch_split(const Ctx *c, const uint32_t *in,
     return CGGI_OK;
 }
 
-// Kernel choice by batch size, in increasing capacity (bootstraps): latency
-// mode with four, then two workgroups per column tile (when on), then one
-// workgroup per 1, 2 or 4 column tiles (the fewest tiles per workgroup that
-// still fit the batch into one wave of workgroups over the CUs).  A count
-// known on the host takes the first option that holds it.  A count read on
-// the device (a level's bootstraps) is bounded by B only, so every option up
-// to the first that holds B is launched, each for the counts in its own
-// range (lo, hi]; the others exit at once.
+// Kernel choice by batch size from the context's plan (entries of
+// increasing capacity; see int8_active_plan).  A count known on the host
+// takes the first entry that holds it.  A count read on the device (a
+// level's bootstraps) is bounded by B only, so every entry up to the first
+// that holds B is launched, each for the counts in its own range (lo, hi];
+// the others exit at once.
 template <int N, int L, int S>
 static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
                             const uint32_t *testv, uint32_t *out, int B,
                             const int32_t *d_count, hipStream_t s)
 {
-    struct Opt {
-        int kind;   // 0, 1: latency mode G = 4, 2; 2, 3, 4: T = 1, 2, 4
-        long cap;
-    };
-    Opt opts[5];
-    int no = 0;
-    if constexpr (N <= 1024) {
-        constexpr long gpt = SplitCfg<N>::GPT;
-        if (c->split_on) {
-            if (c->split_groups[0] > 0)
-                opts[no++] = {0, c->split_groups[0] * gpt};
-            if (c->split_groups[1] > c->split_groups[0])
-                opts[no++] = {1, c->split_groups[1] * gpt};
-        }
-        opts[no++] = {2, (long)c->cus * I8Cfg<N>::GPT};
-        opts[no++] = {3, 2L * c->cus * I8Cfg<N>::GPT};
-    }
-    opts[no++] = {4, 1L << 40};
+    int32_t kind[8], cap[8];
+    const int no = int8_active_plan(c, kind, cap);
     long lo = 0;
     for (int k = 0; k < no; ++k) {
-        const long cap = opts[k].cap;
-        const bool last = B <= cap;
+        const long hi = cap[k];
+        const bool last = B <= hi || k == no - 1;
         if (!d_count && !last) {
-            lo = cap;
+            lo = hi;
             continue;
         }
-        const int Bk = (int)(B < cap ? B : cap);
+        const int Bk = (int)(B < hi ? B : hi);
         const int a = d_count ? (int)lo : 0;
-        const int b = d_count && !last ? (int)cap : INT32_MAX;
-        int rc;
-        switch (opts[k].kind) {
-        case 0:
-            if constexpr (N <= 1024)
+        const int b = d_count && !last ? (int)hi : INT32_MAX;
+        int rc = CGGI_OK;
+        if constexpr (N <= 1024) {
+            switch (kind[k]) {
+            case 0:
                 rc = launch_split<N, L, S, 4>(c, in, testv, out, Bk, d_count,
                                               a, b, s);
-            break;
-        case 1:
-            if constexpr (N <= 1024)
+                break;
+            case 1:
                 rc = launch_split<N, L, S, 2>(c, in, testv, out, Bk, d_count,
                                               a, b, s);
-            break;
-        case 2:
-            if constexpr (N <= 1024)
+                break;
+            case 2:
                 rc = launch_bs_int8_t<N, L, S, 1>(c, in, testv, out, Bk,
                                                   d_count, a, b, s);
-            break;
-        case 3:
-            if constexpr (N <= 1024)
+                break;
+            case 3:
                 rc = launch_bs_int8_t<N, L, S, 2>(c, in, testv, out, Bk,
                                                   d_count, a, b, s);
-            break;
-        default:
+                break;
+            default:
+                rc = launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, Bk,
+                                                  d_count, a, b, s);
+            }
+        } else {
             rc = launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, Bk, d_count,
                                               a, b, s);
         }
         if (rc || last)
             return rc;
-        lo = cap;
+        lo = hi;
     }
     return CGGI_OK;
 }

@@ -46,6 +46,14 @@ struct cggi_ctx {
     size_t x_words[2] = {0, 0};
     uint32_t *x_epoch[2] = {nullptr, nullptr}; // [groups] launch epochs
     uint32_t *x_err = nullptr;    // [1] set when a member's wait timed out
+    // INT8 kernel plan (cggi_ctx_int8_plan): entry k runs the batches of
+    // (cap[k-1], cap[k]] bootstraps with kernel kind[k]; plan_n = 0 selects
+    // the built-in plan.  kind_limit: most bootstraps one launch of each
+    // kind may take (0: kind unavailable for this context).
+    int plan_n = 0;
+    int32_t plan_kind[8] = {};
+    int32_t plan_cap[8] = {};
+    int64_t kind_limit[5] = {0, 0, 0, 0, 0};
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
     int ks_ksj = 0;               // 32-slot K-steps per j
@@ -93,6 +101,10 @@ int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
 // Re-zeroes the latency-mode exchange buffers, epochs and error word
 // (synchronous).
 int int8_split_reset(Ctx *c);
+// The INT8 kernel plan in force (the caller's, or the built-in one), with
+// latency-mode entries dropped while latency mode is off.  Returns the
+// number of entries (at most 8).
+int int8_active_plan(const Ctx *c, int32_t *kind, int32_t *cap);
 
 // Key switch.  in_a/in_b: optional second input added before switching
 // (MUX combine); the plain batch call passes null maps.

@@ -121,4 +121,8 @@ def test_batch_calls_reject_null_context():
     assert L.cggi_ctx_latency_mode(None, 1) == cggi.E_PARAM
     assert L.cggi_ctx_latency_groups(None, None) == cggi.E_PARAM
     assert L.cggi_ctx_check(None) == cggi.E_PARAM
+    assert L.cggi_ctx_int8_plan(None, None, None, 0) == cggi.E_PARAM
+    assert L.cggi_ctx_int8_plan_get(None, None, None, 0, None) == \
+        cggi.E_PARAM
+    assert L.cggi_ctx_int8_limits(None, None) == cggi.E_PARAM
     assert L.cggi_ctx_destroy(None) == cggi.OK
