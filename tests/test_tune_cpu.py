@@ -78,3 +78,12 @@ def test_tune_cli_needs_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(SystemExit, match="no GPU"):
         tune.main(["--params", "toy"])
+
+
+def test_dag_cli_needs_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2306_11006_amd import dag
+    with pytest.raises(SystemExit, match="no GPU"):
+        dag.main(["--gates", "10"])
