@@ -271,6 +271,29 @@ def main():
         line["int8_over_ntt"] = round(r["bootstraps_per_s"] /
                                       rn["bootstraps_per_s"], 3)
     line["forms_bit_identical"] = bool(forms_agree)
+    if "int8" in res and ctx.latency_groups() > 0:
+        # a narrow level: one NAND gate's bootstrap in latency mode (four
+        # workgroups on four CUs) and on the one-workgroup kernel
+        one = wires[:1].clone()
+        big = torch.empty((1, p.N + 1), dtype=torch.int32, device=dev)
+        narrow = {}
+        for mode, on in (("latency_mode_ms", True), ("one_workgroup_ms",
+                                                      False)):
+            ctx.latency_mode(on)
+            ctx.bootstrap("int8", one, big)
+            torch.cuda.synchronize()
+            ctx.profile(True)
+            for _ in range(3):
+                ctx.bootstrap("int8", one, big)
+            bms, bn, _, _ = ctx.profile_read()
+            ctx.profile(False)
+            narrow[mode] = round(bms / max(bn, 1), 3)
+        ctx.latency_mode(True)
+        ctx.check()
+        line["narrow_level"] = dict(
+            bootstraps=1, **narrow,
+            kernels=["k_bootstrap_int8_split<1024, 3, 1, 4>",
+                     "k_bootstrap_int8<1024, 3, 1, 1>"])
     line["kernel_ms"] = {f: {"bootstrap": round(v["bs_kernel_ms"], 4),
                              "keyswitch": round(v["ks_kernel_ms"], 4)}
                          for f, v in res.items()}

@@ -228,6 +228,13 @@ int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
 int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable);
 int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups);
 int cggi_ctx_check(cggi_ctx *ctx);
+/* Sets the context's latency-mode error word from the host at once (not
+ * stream-ordered), as a time-out would: latency-mode kernels still running
+ * stop at their next poll, later ones do nothing (their outputs are left
+ * untouched) until cggi_ctx_check, which then returns CGGI_E_TIMEOUT and
+ * clears the state.  Other INT8 kernels and the NTT form are unaffected.
+ * CGGI_OK also when the context has no latency mode. */
+int cggi_ctx_latency_abort(cggi_ctx *ctx);
 
 /* INT8 kernel plan (autotuning).  The INT8 form has five kernels for a
  * batch: CGGI_K_SPLIT4 and CGGI_K_SPLIT2 (latency mode, four or two

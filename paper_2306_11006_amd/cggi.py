@@ -30,7 +30,8 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_profile_read", "cggi_measure_int8_mfma",
            "cggi_ctx_latency_mode", "cggi_ctx_latency_groups",
            "cggi_ctx_check", "cggi_ctx_int8_plan", "cggi_ctx_int8_plan_get",
-           "cggi_ctx_int8_limits", "cggi_last_error"]
+           "cggi_ctx_int8_limits", "cggi_ctx_latency_abort",
+           "cggi_last_error"]
 
 # INT8 kernel kinds of a plan (cggi_ctx_int8_plan), in the header's order
 KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4")
@@ -82,6 +83,7 @@ def lib():
         L.cggi_ctx_int8_plan.argtypes = [vp, ip, ip, i32]
         L.cggi_ctx_int8_plan_get.argtypes = [vp, ip, ip, i32, ip]
         L.cggi_ctx_int8_limits.argtypes = [vp, ip]
+        L.cggi_ctx_latency_abort.argtypes = [vp]
         L.cggi_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(L, name).restype = ctypes.c_int
@@ -244,6 +246,10 @@ class Context:
         lim = (ctypes.c_int32 * 5)()
         _check(lib().cggi_ctx_int8_limits(self._h, lim))
         return {KINDS[k]: lim[k] for k in range(5)}
+
+    def latency_abort(self):
+        """Stop latency-mode kernels now and refuse new ones until check()."""
+        _check(lib().cggi_ctx_latency_abort(self._h))
 
     def check(self):
         """Wait for the device; raise CggiError(E_TIMEOUT) if a

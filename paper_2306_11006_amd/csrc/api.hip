@@ -490,6 +490,20 @@ int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits)
     return CGGI_OK;
 }
 
+int cggi_ctx_latency_abort(cggi_ctx *ctx)
+{
+    if (!ctx)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    int rc = check_device(ctx);
+    if (rc)
+        return rc;
+    if (!ctx->x_err)
+        return CGGI_OK;
+    const uint32_t one = 1;
+    CGGI_HIP_TRY(hipMemcpy(ctx->x_err, &one, 4, hipMemcpyHostToDevice));
+    return CGGI_OK;
+}
+
 int cggi_ctx_check(cggi_ctx *ctx)
 {
     if (!ctx)

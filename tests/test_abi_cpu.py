@@ -125,4 +125,5 @@ def test_batch_calls_reject_null_context():
     assert L.cggi_ctx_int8_plan_get(None, None, None, 0, None) == \
         cggi.E_PARAM
     assert L.cggi_ctx_int8_limits(None, None) == cggi.E_PARAM
+    assert L.cggi_ctx_latency_abort(None) == cggi.E_PARAM
     assert L.cggi_ctx_destroy(None) == cggi.OK

@@ -152,3 +152,33 @@ def test_latency_mode_repeated_launches_and_graph():
     ctx.check()
     del graph
     ctx.close()
+
+
+def test_latency_mode_abort_and_recovery():
+    """The error word forced from the host (cggi_ctx_latency_abort, no GPU
+    wait involved): a latency-mode launch then writes nothing, other kernels
+    still work, cggi_ctx_check reports CGGI_E_TIMEOUT and clears the state,
+    and the next latency-mode launch is exact again."""
+    import torch
+    from paper_2306_11006_amd import cggi
+    p = params.DEFAULT
+    bsk, ksk, ctx = make_ctx(p, 7500)
+    cts = inputs.uniform_lwe(p, 7501, 5)
+    ref = run_bs(ctx, "ntt", cts)
+    ctx.latency_abort()
+    out = torch.full((5, p.N + 1), 0x5A5A5A5A, dtype=torch.int32,
+                     device="cuda")
+    ctx.bootstrap("int8", cggi.to_device(cts), out)         # latency mode
+    torch.cuda.synchronize()
+    assert bool((out == 0x5A5A5A5A).all()), "aborted launch wrote output"
+    ctx.int8_plan([("tiles1", 2**31 - 1)])                 # not latency mode
+    assert np.array_equal(run_bs(ctx, "int8", cts), ref)
+    ctx.int8_plan(None)
+    with pytest.raises(cggi.CggiError) as e:
+        ctx.check()
+    assert e.value.code == cggi.E_TIMEOUT
+    ctx.check()                                            # cleared
+    for _ in range(2):
+        assert np.array_equal(run_bs(ctx, "int8", cts), ref)
+    ctx.check()
+    ctx.close()
