@@ -272,8 +272,8 @@ def main():
                                       rn["bootstraps_per_s"], 3)
     line["forms_bit_identical"] = bool(forms_agree)
     if "int8" in res and ctx.latency_groups() > 0:
-        # a narrow level: one NAND gate's bootstrap in latency mode (four
-        # workgroups on four CUs) and on the one-workgroup kernel
+        # a narrow level: one NAND gate's bootstrap in latency mode (eight
+        # workgroups on eight CUs) and on the one-workgroup kernel
         one = wires[:1].clone()
         big = torch.empty((1, p.N + 1), dtype=torch.int32, device=dev)
         narrow = {}
@@ -292,7 +292,7 @@ def main():
         ctx.check()
         line["narrow_level"] = dict(
             bootstraps=1, **narrow,
-            kernels=["k_bootstrap_int8_split<1024, 3, 1, 4>",
+            kernels=["k_bootstrap_int8_split<1024, 3, 1, 8>",
                      "k_bootstrap_int8<1024, 3, 1, 1>"])
     line["kernel_ms"] = {f: {"bootstrap": round(v["bs_kernel_ms"], 4),
                              "keyswitch": round(v["ks_kernel_ms"], 4)}

@@ -205,12 +205,13 @@ int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
  * circuit levels; here a narrow batch runs each column tile's blind
  * rotation (1024/N bootstraps) on four workgroups on four CUs, one per
  * block (input component, output component) of the external product, or,
- * for up to twice as many tiles, on two (one per output component), which
- * exchange their partial products after every CMux step through device
- * memory.  Results are bit-identical to the one-workgroup kernel.  Every
- * INT8 call picks its kernel from the batch size: latency mode with four,
- * then two workgroups per tile while the tiles fit, then one workgroup per
- * 1, 2 or 4 tiles.  cggi_bootstrap_batch decides on the host from B;
+ * for at most half as many tiles, on eight (each block's four key limbs in
+ * two pairs), or, for up to twice as many tiles, on two (one per output
+ * component), which exchange their partial products after every CMux step
+ * through device memory.  Results are bit-identical to the one-workgroup kernel.  Every
+ * INT8 call picks its kernel from the batch size: latency mode with eight,
+ * four, then two workgroups per tile while the tiles fit, then one
+ * workgroup per 1, 2 or 4 tiles (or as cggi_ctx_int8_plan sets).  cggi_bootstrap_batch decides on the host from B;
  * cggi_eval_level, whose bootstrap count is known only on the device,
  * launches every candidate up to the one that holds 2G bootstraps, and each
  * runs only if the device count falls in its range.  cggi_ctx_latency_groups
@@ -236,9 +237,10 @@ int cggi_ctx_check(cggi_ctx *ctx);
  * CGGI_OK also when the context has no latency mode. */
 int cggi_ctx_latency_abort(cggi_ctx *ctx);
 
-/* INT8 kernel plan (autotuning).  The INT8 form has five kernels for a
- * batch: CGGI_K_SPLIT4 and CGGI_K_SPLIT2 (latency mode, four or two
- * workgroups per column tile; N <= 1024), CGGI_K_TILES1, CGGI_K_TILES2
+/* INT8 kernel plan (autotuning).  The INT8 form has six kernels for a
+ * batch: CGGI_K_SPLIT8, CGGI_K_SPLIT4 and CGGI_K_SPLIT2 (latency mode,
+ * eight, four or two workgroups per column tile; N <= 1024),
+ * CGGI_K_TILES1, CGGI_K_TILES2
  * (one workgroup per one or two column tiles; N <= 1024) and CGGI_K_TILES4
  * (four tiles, or one bootstrap per workgroup at N = 2048).  A plan is a
  * list of entries (kinds[k], caps[k]) with strictly increasing caps: entry
@@ -248,8 +250,9 @@ int cggi_ctx_latency_abort(cggi_ctx *ctx);
  * bootstraps one launch of each kind may take, 0 if the kind is
  * unavailable; latency-mode limits keep every workgroup resident).  All
  * kinds give bit-identical results; the plan only changes speed.  count = 0
- * restores the built-in plan (latency mode with four, then two workgroups
- * while the tiles fit, then 1, 2 or 4 tiles per workgroup by batch width;
+ * restores the built-in plan (latency mode with eight, four, then two
+ * workgroups while the tiles fit, then 1, 2 or 4 tiles per workgroup by
+ * batch width;
  * see cggi_ctx_latency_mode).  While latency mode is off its entries are
  * skipped and their batches go to the next entry.  cggi_ctx_int8_plan_get
  * writes the plan in force (at most max entries; count = entries).  Host
@@ -261,13 +264,14 @@ enum {
     CGGI_K_SPLIT2 = 1,
     CGGI_K_TILES1 = 2,
     CGGI_K_TILES2 = 3,
-    CGGI_K_TILES4 = 4
+    CGGI_K_TILES4 = 4,
+    CGGI_K_SPLIT8 = 5
 };
 int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
                        const int32_t *caps, int32_t count);
 int cggi_ctx_int8_plan_get(const cggi_ctx *ctx, int32_t *kinds,
                            int32_t *caps, int32_t max, int32_t *count);
-int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits /* [5] */);
+int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits /* [6] */);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);

@@ -34,7 +34,7 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_last_error"]
 
 # INT8 kernel kinds of a plan (cggi_ctx_int8_plan), in the header's order
-KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4")
+KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4", "split8")
 INT32_MAX = 2**31 - 1
 
 
@@ -243,9 +243,9 @@ class Context:
     def int8_limits(self):
         """{kind name: most bootstraps one launch of it may take} (0 when
         the kind is unavailable)."""
-        lim = (ctypes.c_int32 * 5)()
+        lim = (ctypes.c_int32 * len(KINDS))()
         _check(lib().cggi_ctx_int8_limits(self._h, lim))
-        return {KINDS[k]: lim[k] for k in range(5)}
+        return {KINDS[k]: lim[k] for k in range(len(KINDS))}
 
     def latency_abort(self):
         """Stop latency-mode kernels now and refuse new ones until check()."""

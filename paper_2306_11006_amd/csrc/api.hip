@@ -115,7 +115,7 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 3; ++v) {
         (void)hipFree(c->x_buf[v]);
         (void)hipFree(c->x_epoch[v]);
     }
@@ -411,9 +411,9 @@ int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups)
 {
     if (!ctx || !groups)
         return set_error(CGGI_E_PARAM, "ctx or groups is NULL");
-    const int g = ctx->split_groups[0] > ctx->split_groups[1]
-                      ? ctx->split_groups[0]
-                      : ctx->split_groups[1];
+    int g = 0;
+    for (int v = 0; v < 3; ++v)
+        g = ctx->split_groups[v] > g ? ctx->split_groups[v] : g;
     *groups = ctx->split_on ? g : 0;
     return CGGI_OK;
 }
@@ -434,7 +434,7 @@ int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
         return set_error(CGGI_E_PARAM, "count must be in [0, 8] and kinds, "
                                        "caps non-NULL");
     for (int k = 0; k < count; ++k) {
-        if (kinds[k] < 0 || kinds[k] > 4 || ctx->kind_limit[kinds[k]] <= 0)
+        if (kinds[k] < 0 || kinds[k] > 5 || ctx->kind_limit[kinds[k]] <= 0)
             return set_error(CGGI_E_PARAM, "plan entry " + std::to_string(k) +
                                                ": kernel kind unavailable");
         if (caps[k] < 1 || (k > 0 && caps[k] <= caps[k - 1]))
@@ -483,7 +483,7 @@ int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits)
 {
     if (!ctx || !limits)
         return set_error(CGGI_E_PARAM, "ctx or limits is NULL");
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 6; ++k)
         limits[k] = ctx->kind_limit[k] > INT32_MAX
                         ? INT32_MAX
                         : (int32_t)ctx->kind_limit[k];

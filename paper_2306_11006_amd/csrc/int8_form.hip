@@ -562,14 +562,21 @@ template <int N> struct SplitCfg {
     static constexpr int WORDS = GPT * N;   // partial words per member
 };
 
-// G = 4 members per tile as above; G = 2 (for batches up to twice as
-// wide) gives member m = c' both input components.
+// G = 4 members per tile as above; G = 8 (for batches of at most half as
+// many tiles) splits each member's four key limbs into two pairs; G = 2 (for
+// batches up to twice as wide) gives member m = c' both input components.
+template <int G> struct SplitRole {
+    static constexpr int LPM = G == 8 ? 2 : 4;       // key limbs per member
+    static constexpr bool ONE_C = G != 2;            // one input component
+};
+
 template <int N, int G>
 static size_t split_smem_bytes(int R, int n)
 {
     using C = SplitCfg<N>;
-    const int RM = G == 4 ? R / 2 : R;               // digit rows per member
-    size_t b = (size_t)RM * 16 * C::CLEN * 4         // key windows of a step
+    using Ro = SplitRole<G>;
+    const int RM = Ro::ONE_C ? R / 2 : R;            // digit rows per member
+    size_t b = (size_t)RM * 4 * Ro::LPM * C::CLEN * 4 // key windows of a step
                + (size_t)C::GPT * 3 * C::AST * 4     // accumulators + partial
                + (size_t)C::GPT * RM * 2 * N;        // digit operands
     return b + (((size_t)C::GPT * (n + 1) * 2 + 15) & ~(size_t)15);
@@ -585,7 +592,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     unsigned long long *xb, uint32_t *epoch, uint32_t *err, int n, int beta,
     int l_rt, int S_rt)
 {
-    static_assert(G == 4 || G == 2, "four or two members per tile");
+    static_assert(G == 8 || G == 4 || G == 2, "8, 4 or 2 members per tile");
+    constexpr int LPM = SplitRole<G>::LPM;
+    constexpr bool ONE_C = SplitRole<G>::ONE_C;
     using C = SplitCfg<N>;
     constexpr int NB = C::NB, GPT = C::GPT, ND = C::ND, EW = C::EW;
     constexpr int CW = C::CW, CLEN = C::CLEN, AST = C::AST;
@@ -595,11 +604,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int SS = L ? S : S_rt;
     const int R = 2 * l * SS;
     const int RH = l * SS;                 // digit rows of one component
-    const int RM = G == 4 ? RH : R;        // digit rows of this member
+    const int RM = ONE_C ? RH : R;         // digit rows of this member
 
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem);  // [RM][4][4][CLEN]
-    uint32_t *acc = ecop + RM * 16 * CLEN;                  // [GPT][2][AST]
+    uint32_t *ecop = reinterpret_cast<uint32_t *>(smem); // [RM][LPM][4][CLEN]
+    uint32_t *acc = ecop + RM * LPM * 4 * CLEN;             // [GPT][2][AST]
     uint32_t *part = acc + GPT * 2 * AST;                   // [GPT][AST]
     int8_t *dig = reinterpret_cast<int8_t *>(part + GPT * AST);
     uint16_t *ms =
@@ -619,8 +628,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const int g0 = grp * GPT;
     if (g0 >= count)
         return;
-    const int cp = G == 4 ? member & 1 : member;
-    const int ch = G == 4 ? member >> 1 : 0;    // first input component
+    const int cp = G == 2 ? member : member & 1;          // output component
+    const int ch = G == 2 ? 0 : (member >> 1) & 1;        // input component
+    const int q0 = G == 8 ? 2 * (member >> 2) : 0;        // first key limb
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
 
@@ -663,9 +673,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     // step i + 1's are read while step i's partials are exchanged (the two
     // latencies overlap) and then written to LDS in four byte-shifted
     // copies; no read stays in flight from one step into the next
-    constexpr int RMAX = (L ? 2 * L * S : SPLIT_RMAX) / (G == 4 ? 2 : 1);
-    constexpr int PER_T = (RMAX * 4 * CW + T - 1) / T;
-    const int items = RM * 4 * CW;
+    constexpr int RMAX = (L ? 2 * L * S : SPLIT_RMAX) / (ONE_C ? 2 : 1);
+    constexpr int PER_T = (RMAX * LPM * CW + T - 1) / T;
+    const int items = RM * LPM * CW;
     uint32_t pre_lo[PER_T], pre_hi[PER_T];
     auto fetch = [&](int i) {
         const uint32_t *src = reinterpret_cast<const uint32_t *>(key) +
@@ -674,9 +684,10 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         for (int k = 0; k < PER_T; ++k) {
             // surplus lanes re-read the last word (never stored)
             int item = min(tid + k * T, items - 1);
-            int kb = item / (4 * CW), rem = item - kb * (4 * CW);
+            int kb = item / (LPM * CW), rem = item - kb * (LPM * CW);
             int q = rem / CW, w = rem - q * CW;
-            const uint32_t *sp = src + ((size_t)kb * 8 + cp * 4 + q) * EW + w;
+            const uint32_t *sp =
+                src + ((size_t)kb * 8 + cp * 4 + q0 + q) * EW + w;
             pre_lo[k] = sp[0];
             pre_hi[k] = sp[1];
         }
@@ -686,9 +697,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         for (int k = 0; k < PER_T; ++k) {
             int item = tid + k * T;
             if (item < items) {
-                int kb = item / (4 * CW), rem = item - kb * (4 * CW);
+                int kb = item / (LPM * CW), rem = item - kb * (LPM * CW);
                 int q = rem / CW, w = rem - q * CW;
-                uint32_t *d = ecop + (kb * 4 + q) * 4 * CLEN + w;
+                uint32_t *d = ecop + (kb * LPM + q) * 4 * CLEN + w;
                 d[0] = pre_lo[k];
                 d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
                 d[2 * CLEN] =
@@ -720,7 +731,7 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         lds_barrier();   // ACC and this step's key windows complete
         if (s_stop)
             break;
-        if constexpr (G == 4)
+        if constexpr (ONE_C)
             decompose_acc<N, L, S, GPT, T, 1>(acc, dig, ms, i, n, l, SS, RH,
                                               beta, dig_off, bmask, bhalf,
                                               tid, ch);
@@ -731,11 +742,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
         lds_barrier();
 
         // ---- K loop over (digit row of the member, block offset) --------
-        auto load = [&](int idx, v4i (&af)[4], v4i &bf) {
+        auto load = [&](int idx, v4i (&af)[LPM], v4i &bf) {
             const int kb = idx / ND, dl = dl0 + idx % ND;
-            const uint32_t *eb = ecop + kb * 16 * CLEN + a_lane + 8 * dl;
+            const uint32_t *eb = ecop + kb * LPM * 4 * CLEN + a_lane + 8 * dl;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < LPM; ++q) {
                 const uint32_t *apq = eb + q * 4 * CLEN;
                 af[q][0] = (int)apq[0];
                 af[q][1] = (int)apq[1];
@@ -748,11 +759,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                                                 sg + Mb * 16);
         };
         const int K = RM * ND;
-        v16i Cq[4] = {};
-        v4i af0[4], af1[4], bf0, bf1;
-        auto mfma4 = [&](const v4i (&af)[4], const v4i &bf) {
+        v16i Cq[LPM] = {};
+        v4i af0[LPM], af1[LPM], bf0, bf1;
+        auto mfma4 = [&](const v4i (&af)[LPM], const v4i &bf) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < LPM; ++q)
                 Cq[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[q], bf, Cq[q],
                                                               0, 0, 0);
         };
@@ -768,16 +779,17 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                 load(idx + 2, af0, bf0);
             mfma4(af1, bf1);
         }
-        // ---- fold the four limbs, add this wave's block offsets ---------
+        // ---- fold the member's limbs, add this wave's block offsets ------
         {
             uint32_t *pp = part + glc * AST + 33 * Jc;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 int row = 8 * (v >> 2) + 4 * hh + (v & 3);
-                uint32_t xv = (uint32_t)Cq[0][v] + ((uint32_t)Cq[1][v] << 8) +
-                              ((uint32_t)Cq[2][v] << 16) +
-                              ((uint32_t)Cq[3][v] << 24);
-                atomicAdd(&pp[row], xv);
+                uint32_t xv = 0;
+#pragma unroll
+                for (int q = 0; q < LPM; ++q)
+                    xv += (uint32_t)Cq[q][v] << (8 * q);
+                atomicAdd(&pp[row], xv << (8 * q0));
             }
         }
         lds_barrier();   // partial complete; key windows free
@@ -855,10 +867,11 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                 const int gl = m / N, j = m - gl * N;
 #pragma unroll
                 for (int c2 = 0; c2 < 2; ++c2) {
-                    // the members with output component c2
-                    uint32_t add = (uint32_t)wv[c2][k];
-                    if constexpr (G == 4)
-                        add += (uint32_t)wv[c2 + 2][k];
+                    // the members with output component c2: m & 1 == c2
+                    uint32_t add = 0;
+#pragma unroll
+                    for (int mb = c2; mb < G; mb += 2)
+                        add += (uint32_t)wv[mb][k];
                     acc[(gl * 2 + c2) * AST + ap(j)] += add;
                 }
             }
@@ -945,7 +958,10 @@ static int split_setup_t(Ctx *c, hipStream_t s)
     int rc = split_setup_g<N, L, S, 4>(c, 0, s);
     if (!rc)
         rc = split_setup_g<N, L, S, 2>(c, 1, s);
-    if (rc || (!c->split_groups[0] && !c->split_groups[1]))
+    if (!rc)
+        rc = split_setup_g<N, L, S, 8>(c, 2, s);
+    if (rc || (!c->split_groups[0] && !c->split_groups[1] &&
+               !c->split_groups[2]))
         return rc;
     if (hipMalloc(&c->x_err, 4) != hipSuccess)
         return set_error(CGGI_E_NOMEM, "hipMalloc of the latency-mode "
@@ -973,7 +989,7 @@ int int8_split_reset(Ctx *c)
 {
     if (!c->x_err)
         return CGGI_OK;
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < 3; ++v) {
         if (!c->x_buf[v])
             continue;
         CGGI_HIP_TRY(hipMemset(c->x_buf[v], 0, c->x_words[v] * 8));
@@ -1010,6 +1026,7 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     c->kind_limit[2] = N <= 1024 ? ANY : 0;
     c->kind_limit[3] = N <= 1024 ? ANY : 0;
     c->kind_limit[4] = ANY;
+    c->kind_limit[5] = (int64_t)c->split_groups[2] * gpt;
     return CGGI_OK;
 }
 
@@ -1024,11 +1041,18 @@ int int8_active_plan(const Ctx *c, int32_t *kind, int32_t *cap)
         }
         n0 = c->plan_n;
     } else {
-        // built-in: latency mode with four, then two workgroups per tile
-        // while the tiles fit; then the fewest tiles per workgroup that
-        // still fit the batch into one wave of workgroups over the CUs
+        // built-in: latency mode with eight workgroups per tile up to half
+        // their limit (beyond that their longer exchange outweighs the
+        // shorter K loop: 2.87 vs 3.05 ms at 1 bootstrap, 3.48 vs 3.25 ms
+        // at 32, N = 1024), four, then two while the tiles fit; then the
+        // fewest tiles per workgroup that still fit the batch into one wave
+        // of workgroups over the CUs
         const int64_t gpt = c->sh.N <= 1024 ? 1024 / c->sh.N : 1;
-        if (c->kind_limit[0] > 0) {
+        if (c->kind_limit[5] > 1) {
+            k0[n0] = 5;
+            c0[n0++] = (int32_t)(c->kind_limit[5] / 2);
+        }
+        if (c->kind_limit[0] > c->kind_limit[5] / 2) {
             k0[n0] = 0;
             c0[n0++] = (int32_t)c->kind_limit[0];
         }
@@ -1047,7 +1071,7 @@ int int8_active_plan(const Ctx *c, int32_t *kind, int32_t *cap)
     }
     int n = 0;
     for (int k = 0; k < n0; ++k) {
-        if (!c->split_on && k0[k] <= 1)
+        if (!c->split_on && (k0[k] <= 1 || k0[k] == 5))
             continue;          // its batches go to the next entry
         kind[n] = k0[k];
         cap[n++] = c0[k];
@@ -1097,7 +1121,7 @@ static int launch_split(const Ctx *c, const uint32_t *in,
                         const int32_t *d_count, int lo, int hi, hipStream_t s)
 {
     const Shape &sh = c->sh;
-    const int v = G == 4 ? 0 : 1;
+    const int v = G == 4 ? 0 : (G == 2 ? 1 : 2);
     const int groups = (B + SplitCfg<N>::GPT - 1) / SplitCfg<N>::GPT;
     const int grid = (groups + 7) / 8 * 8 * G;
     hipLaunchKernelGGL((k_bootstrap_int8_split<N, L, S, G>), dim3(grid),
@@ -1142,6 +1166,10 @@ static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
                 break;
             case 1:
                 rc = launch_split<N, L, S, 2>(c, in, testv, out, Bk, d_count,
+                                              a, b, s);
+                break;
+            case 5:
+                rc = launch_split<N, L, S, 8>(c, in, testv, out, Bk, d_count,
                                               a, b, s);
                 break;
             case 2:

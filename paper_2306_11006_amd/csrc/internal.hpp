@@ -38,13 +38,13 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
-    // INT8 latency mode (one tile over G = 4 or 2 workgroups, N <= 1024);
-    // index 0: G = 4, index 1: G = 2
+    // INT8 latency mode (one tile over G = 8, 4 or 2 workgroups, N <= 1024);
+    // index 0: G = 4, index 1: G = 2, index 2: G = 8
     bool split_on = true;         // cggi_ctx_latency_mode
-    int split_groups[2] = {0, 0}; // most tile groups per launch (0: none)
-    unsigned long long *x_buf[2] = {nullptr, nullptr}; // [groups][2][G][1024]
-    size_t x_words[2] = {0, 0};
-    uint32_t *x_epoch[2] = {nullptr, nullptr}; // [groups] launch epochs
+    int split_groups[3] = {0, 0, 0}; // most tile groups per launch (0: none)
+    unsigned long long *x_buf[3] = {}; // [groups][2][G][1024]
+    size_t x_words[3] = {0, 0, 0};
+    uint32_t *x_epoch[3] = {};    // [groups] launch epochs
     uint32_t *x_err = nullptr;    // [1] set when a member's wait timed out
     // INT8 kernel plan (cggi_ctx_int8_plan): entry k runs the batches of
     // (cap[k-1], cap[k]] bootstraps with kernel kind[k]; plan_n = 0 selects
@@ -53,7 +53,7 @@ struct cggi_ctx {
     int plan_n = 0;
     int32_t plan_kind[8] = {};
     int32_t plan_cap[8] = {};
-    int64_t kind_limit[5] = {0, 0, 0, 0, 0};
+    int64_t kind_limit[6] = {0, 0, 0, 0, 0, 0};
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
     int ks_ksj = 0;               // 32-slot K-steps per j

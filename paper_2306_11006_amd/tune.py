@@ -1,8 +1,8 @@
 """Autotuner of the int8 form's kernel plan (and of the form per level width).
 
-The int8 form has five kernels for a batch of bootstraps (cggi.KINDS):
-latency mode with four or two workgroups per column tile, and one workgroup
-per 1, 2 or 4 column tiles.  All give bit-identical results; which is
+The int8 form has six kernels for a batch of bootstraps (cggi.KINDS):
+latency mode with eight, four or two workgroups per column tile, and one
+workgroup per 1, 2 or 4 column tiles.  All give bit-identical results; which is
 fastest depends on the batch width, the parameter set and the GPU.  The
 tuner times every kernel that can take each width of a grid (one
 cggi_bootstrap_batch per measurement under a plan that forces the kernel,
@@ -39,7 +39,8 @@ def widths_grid(limits, cus, gpt, max_width=4096):
     one-, two- and four-tiles-per-CU boundaries (each with its successor),
     up to max_width."""
     pts = {1 << k for k in range(max_width.bit_length()) if 1 << k <= max_width}
-    for b in (limits.get("split4", 0), limits.get("split2", 0), cus * gpt,
+    for b in (limits.get("split8", 0), limits.get("split4", 0),
+              limits.get("split2", 0), cus * gpt,
               2 * cus * gpt, 4 * cus * gpt):
         for w in (b, b + 1):
             if 1 <= w <= max_width:
@@ -60,7 +61,7 @@ def plan_from_winners(winners):
             plan.append((k, w))
     if not plan:
         return [("tiles4", MAX_CAP)]
-    if plan[-1][0] in ("split4", "split2"):
+    if plan[-1][0].startswith("split"):
         plan.append(("tiles4", MAX_CAP))
     else:
         plan[-1] = (plan[-1][0], MAX_CAP)
@@ -97,7 +98,7 @@ def cache_dir():
 
 def _force(ctx, kind, limits):
     """Plan that sends every batch within the kind's limit to `kind`."""
-    if kind in ("split4", "split2"):
+    if kind.startswith("split"):
         ctx.int8_plan([(kind, limits[kind]), ("tiles4", MAX_CAP)])
     else:
         ctx.int8_plan([(kind, MAX_CAP)])

@@ -1,6 +1,6 @@
 """Latency mode of the int8 form: a narrow batch runs each column tile's
-blind rotation on four (or, for up to twice as many tiles, two) workgroups
-that exchange partial products after every CMux step.  Bit-exact against
+blind rotation on eight, four or (for up to twice as many tiles) two
+workgroups that exchange partial products after every CMux step.  Bit-exact against
 the oracle and the NTT form, identical to the one-workgroup kernel, at every
 N <= 1024 and digit shape (specialised and generic builds), over partial
 tiles, repeated launches (launch epochs), and HIP-graph replays of a whole
@@ -41,7 +41,8 @@ def make_ctx(p, seed):
 
 CASES = [
     # (parameter set, batch sizes): N = 1024 (l=3, S=1 build), N = 256 with
-    # Bg = 2^8 (two sub-digits, the l=2 S=2 build, four bootstraps per tile)
+    # Bg = 2^8 (two sub-digits, the l=2 S=2 build, four bootstraps per tile);
+    # the smallest batches take eight workgroups per tile, the largest two
     (params.DEFAULT, (1, 3, 64, 100, 128)),
     (params.TOY, (1, 5, 255, 300)),
     (dataclasses.replace(params.DEFAULT, name="n512_N512", n=512, N=512),

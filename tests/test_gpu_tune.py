@@ -31,7 +31,7 @@ def run_bs(ctx, form, cts):
 
 
 def force(ctx, kind, limits):
-    if kind in ("split4", "split2"):
+    if kind.startswith("split"):
         ctx.int8_plan([(kind, limits[kind]), ("tiles4", BIG)])
     else:
         ctx.int8_plan([(kind, BIG)])
@@ -44,7 +44,8 @@ def test_every_kind_same_bits(O, p):
     ctx = cggi.Context(p, cggi.to_device(bsk), cggi.to_device(ksk))
     limits = ctx.int8_limits()
     assert all(limits[k] > 0 for k in cggi.KINDS), limits
-    widths = (1, 7, limits["split4"], 300, limits["split2"])
+    widths = (1, 7, limits["split8"], limits["split4"], 300,
+              limits["split2"])
     cts = inputs.uniform_lwe(p, 8101, max(widths))
     for w in widths:
         x = cts[:w]
@@ -96,7 +97,8 @@ def test_invalid_plans_rejected():
     cl = cggi.Context(params.LARGE, cggi.to_device(bl), cggi.to_device(kl),
                       forms=("int8",))
     lim = cl.int8_limits()
-    assert lim["tiles4"] > 0 and all(lim[k] == 0 for k in cggi.KINDS[:4])
+    assert lim["tiles4"] > 0 and all(lim[k] == 0 for k in cggi.KINDS
+                                     if k != "tiles4")
     assert cl.int8_plan_get() == [("tiles4", BIG)]
     with pytest.raises(cggi.CggiError):
         cl.int8_plan([("tiles1", BIG)])

@@ -5,7 +5,7 @@ import pytest
 
 from paper_2306_11006_amd import cggi, params, tune
 
-LIMITS = {"split4": 64, "split2": 128, "tiles1": 2**31 - 1,
+LIMITS = {"split8": 32, "split4": 64, "split2": 128, "tiles1": 2**31 - 1,
           "tiles2": 2**31 - 1, "tiles4": 2**31 - 1}
 
 
@@ -13,7 +13,7 @@ def valid(plan, limits=LIMITS):
     caps = [c for _, c in plan]
     assert all(a < b for a, b in zip(caps, caps[1:]))
     assert caps[-1] >= 1 << 24
-    assert plan[-1][0] not in ("split4", "split2")
+    assert not plan[-1][0].startswith("split")
     for k, c in plan:
         assert k in cggi.KINDS and 1 <= c <= limits[k]
 
@@ -21,7 +21,8 @@ def valid(plan, limits=LIMITS):
 def test_grid_holds_powers_and_boundaries():
     g = tune.widths_grid(LIMITS, cus=256, gpt=1, max_width=4096)
     assert g == sorted(set(g))
-    for w in (1, 2, 64, 65, 128, 129, 256, 257, 512, 513, 1024, 1025, 4096):
+    for w in (1, 2, 32, 33, 64, 65, 128, 129, 256, 257, 512, 513, 1024,
+              1025, 4096):
         assert w in g, w
     assert max(g) == 4096
     g4 = tune.widths_grid(LIMITS, cus=256, gpt=4, max_width=300)
