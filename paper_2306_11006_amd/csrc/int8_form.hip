@@ -548,6 +548,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 // clears it.  The members of a group are placed on one XCD (blocks of one
 // group are congruent mod 8), which keeps the exchange in one L2.
 constexpr int SPLIT_THREADS = 512;
+constexpr int SPLIT_STATIC_LDS = 64;     // bound on the kernel's static LDS
 constexpr int SPLIT_RMAX = 8;            // digit polynomials per step
 constexpr unsigned long long SPLIT_WAIT_TICKS = 100000000ull;   // 1 s
 
@@ -928,12 +929,16 @@ static int split_setup_g(Ctx *c, int v, hipStream_t s)
     const Shape &sh = c->sh;
     const size_t smem = split_smem_bytes<N, G>(sh.R, sh.n);
     // (the kernel also holds 8 bytes of static LDS)
-    if (sh.R > SPLIT_RMAX || smem + 64 > 160 * 1024)
+    if (sh.R > SPLIT_RMAX || smem + SPLIT_STATIC_LDS > 160 * 1024)
         return CGGI_OK;                       // this variant unavailable
     const void *fn =
         reinterpret_cast<const void *>(&k_bootstrap_int8_split<N, L, S, G>);
+    // the attribute belongs to the kernel, not the context: set it to the
+    // most any context may launch with, so that contexts of different n
+    // can share the instantiation
     CGGI_HIP_TRY(hipFuncSetAttribute(
-        fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+        fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+        160 * 1024 - SPLIT_STATIC_LDS));
     int occ = 0;
     CGGI_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
         &occ, fn, SPLIT_THREADS, smem));

@@ -183,3 +183,22 @@ def test_latency_mode_abort_and_recovery():
         assert np.array_equal(run_bs(ctx, "int8", cts), ref)
     ctx.check()
     ctx.close()
+
+
+def test_latency_mode_contexts_of_different_sizes():
+    """Two contexts sharing a latency-mode kernel build with different LDS
+    needs (n = 1023 and n = 630 at N = 1024), the larger created first and
+    used after the smaller: both stay exact."""
+    import dataclasses
+    p_big = dataclasses.replace(params.DEFAULT, name="n1023", n=1023)
+    p = params.DEFAULT
+    bb, kb, cb = make_ctx(p_big, 7600)
+    bs, ks, cs = make_ctx(p, 7601)
+    xb = inputs.uniform_lwe(p_big, 7602, 3)
+    xs = inputs.uniform_lwe(p, 7603, 3)
+    for ctx, x in ((cs, xs), (cb, xb), (cs, xs)):
+        want = run_bs(ctx, "ntt", x)
+        assert np.array_equal(run_bs(ctx, "int8", x), want)
+        ctx.check()
+    cb.close()
+    cs.close()
