@@ -9,9 +9,9 @@
 // result equals the integer product, and its low 32 bits are the product
 // mod 2^32.
 //
-// Layout: one workgroup of 256 threads owns one bootstrap.  LDS holds the
-// accumulator (2 x N u32), the 2l digit transforms (2l x N u64) and the two
-// product transforms (2 x N u64).  The transformed key row of step i
+// Layout: one workgroup (256 to 1024 threads by N) owns one bootstrap.
+// LDS holds the accumulator (2 x N u32), the 2l digit transforms (2l x N
+// u64) and the two product transforms (2 x N u64).  The transformed key row of step i
 // ([2l][2][N] u64) streams from L2 / Infinity Cache; it is shared by every
 // workgroup.
 #include "goldilocks.hpp"
@@ -23,7 +23,16 @@ namespace cggi {
 
 namespace {
 
-constexpr int NTT_THREADS = 256;
+constexpr int NTT_THREADS = 256;   // table kernels
+
+// Threads of a bootstrap workgroup.  The butterflies are VALU-bound with an
+// LDS round trip every three stages, so more waves per SIMD hide more of
+// the LDS latency and barrier skew.  At N = 2048 the workgroup's LDS
+// (113 KB at l = 2) leaves room for one per CU: 16 waves (four per SIMD,
+// within the 96-VGPR budget) run 1.45x faster than 4.  At N = 1024 two
+// workgroups share a CU: 8 waves each (four per SIMD) run 1.1x faster than
+// 4.  Every loop below strides by the thread count, so any count is exact.
+constexpr int bs_threads(int N) { return N >= 2048 ? 1024 : (N >= 1024 ? 512 : 256); }
 constexpr uint64_t G_PAPER = 12037493425763644479ull; // order 2^32 mod Q
 
 unsigned bitrev(unsigned x, int bits)
@@ -62,7 +71,7 @@ __device__ __forceinline__ void fwd_block(uint64_t (&v)[1 << NS], int m0, int i,
     }
 }
 
-template <int N, int NS>
+template <int N, int NS, int TH = NTT_THREADS>
 __device__ __forceinline__ void fwd_pass(uint64_t *a, int P, int s0,
                                          const uint64_t *__restrict__ tw)
 {
@@ -71,7 +80,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t *a, int P, int s0,
     const int t0 = N >> (s0 + 1);           // half-span at the first stage
     const int stride = (2 * t0) >> NS;      // distance between block elements
     const int per_poly = N / K;
-    for (int idx = threadIdx.x; idx < P * per_poly; idx += NTT_THREADS) {
+    for (int idx = threadIdx.x; idx < P * per_poly; idx += TH) {
         const int poly = idx / per_poly, r = idx - poly * per_poly;
         const int i = r / stride, off = r - i * stride;
         uint64_t *x = a + poly * N + 2 * t0 * i + off;
@@ -103,7 +112,7 @@ __device__ __forceinline__ void ntt_fwd(uint64_t *a, int P,
 
 // Forward stages 3 .. log2 N - 2 of P polynomials (stages 0..2 are fused
 // with the decomposition, the last one with the pointwise product).
-template <int N>
+template <int N, int TH>
 __device__ __forceinline__ void ntt_fwd_middle(uint64_t *a, int P,
                                                const uint64_t *__restrict__ tw)
 {
@@ -111,11 +120,11 @@ __device__ __forceinline__ void ntt_fwd_middle(uint64_t *a, int P,
     constexpr int END = LOGN - 1;
     int s = 3;
     for (; s + 3 <= END; s += 3)
-        fwd_pass<N, 3>(a, P, s, tw);
+        fwd_pass<N, 3, TH>(a, P, s, tw);
     if (END - s == 2)
-        fwd_pass<N, 2>(a, P, s, tw);
+        fwd_pass<N, 2, TH>(a, P, s, tw);
     else if (END - s == 1)
-        fwd_pass<N, 1>(a, P, s, tw);
+        fwd_pass<N, 1, TH>(a, P, s, tw);
 }
 
 // NS inverse (Gentleman-Sande) stages from stage u0 on the two product
@@ -123,7 +132,7 @@ __device__ __forceinline__ void ntt_fwd_middle(uint64_t *a, int P,
 // twi[h + i] = psi^-bitrev(h + i)), in place, or, for the last pass, added
 // into the torus accumulator as the centred lift (the 1/N scaling is folded
 // into the transformed key).
-template <int N, int NS, bool TO_ACC>
+template <int N, int NS, bool TO_ACC, int TH>
 __device__ __forceinline__ void inv_pass(uint64_t *a, int u0,
                                          const uint64_t *__restrict__ twi,
                                          uint32_t *acc)
@@ -132,7 +141,7 @@ __device__ __forceinline__ void inv_pass(uint64_t *a, int u0,
     const int t0 = 1 << u0;                 // half-span at the first stage
     const int span = t0 * K;                // block of the pass
     constexpr int per_poly = N / K;
-    for (int idx = threadIdx.x; idx < 2 * per_poly; idx += NTT_THREADS) {
+    for (int idx = threadIdx.x; idx < 2 * per_poly; idx += TH) {
         const int poly = idx / per_poly, r = idx - poly * per_poly;
         const int blk = r / t0, off = r - blk * t0;
         const int base = poly * N + blk * span + off;
@@ -167,7 +176,7 @@ __device__ __forceinline__ void inv_pass(uint64_t *a, int u0,
 
 // Inverse stages 1 .. log2 N - 1 (stage 0 is fused with the pointwise
 // product); the last pass adds the result into the accumulator.
-template <int N>
+template <int N, int TH>
 __device__ __forceinline__ void ntt_inv_to_acc(uint64_t *a,
                                                const uint64_t *__restrict__ twi,
                                                uint32_t *acc)
@@ -179,14 +188,14 @@ __device__ __forceinline__ void ntt_inv_to_acc(uint64_t *a,
     int u = 1;
     for (int f = 0; f < FULL; ++f, u += 3) {
         if (REM == 0 && f == FULL - 1)
-            inv_pass<N, 3, true>(a, u, twi, acc);
+            inv_pass<N, 3, true, TH>(a, u, twi, acc);
         else
-            inv_pass<N, 3, false>(a, u, twi, acc);
+            inv_pass<N, 3, false, TH>(a, u, twi, acc);
     }
     if (REM == 2)
-        inv_pass<N, 2, true>(a, u, twi, acc);
+        inv_pass<N, 2, true, TH>(a, u, twi, acc);
     else if (REM == 1)
-        inv_pass<N, 1, true>(a, u, twi, acc);
+        inv_pass<N, 1, true, TH>(a, u, twi, acc);
 }
 
 // bsk -> NTT form, times 1/N (the inverse transform then needs no scaling)
@@ -213,8 +222,8 @@ __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
 }
 
 // One bootstrap per workgroup.
-template <int N>
-__global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
+template <int N, int TH = bs_threads(N)>
+__global__ __launch_bounds__(TH) void k_bootstrap_ntt(
     const uint64_t *__restrict__ bsk_ntt, const uint64_t *__restrict__ tw,
     const uint64_t *__restrict__ twi,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
@@ -236,14 +245,14 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
         return;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
     const uint32_t *ct = in + (size_t)g * (n + 1);
-    for (int i = threadIdx.x; i <= n; i += NTT_THREADS)
+    for (int i = threadIdx.x; i <= n; i += TH)
         ms[i] = (uint16_t)modswitch(ct[i], LOG2_2N);
     __syncthreads();
 
     // ACC = (0, X^(2N - b~) * v)
     {
         int e = (2 * N - ms[n]) & (2 * N - 1);
-        for (int m = threadIdx.x; m < N; m += NTT_THREADS) {
+        for (int m = threadIdx.x; m < N; m += TH) {
             uint32_t v = testv ? testv[m] : (1u << 29);
             int t = m + e;
             if (t >= 2 * N) {
@@ -273,7 +282,7 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
         // takes the 8 coefficients m = off + k N/8 of one component, forms
         // X^e ACC - ACC there, and runs each digit polynomial's radix-8
         // block in registers
-        for (int idx = threadIdx.x; idx < 2 * (N / 8); idx += NTT_THREADS) {
+        for (int idx = threadIdx.x; idx < 2 * (N / 8); idx += TH) {
             const int c = idx / (N / 8), off = idx - c * (N / 8);
             const uint32_t *ac = acc + c * N;
             uint32_t w[8];
@@ -299,12 +308,12 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
         }
         __syncthreads();
         // (2) forward stages 3 .. log2 N - 2
-        ntt_fwd_middle<N>(dig, L2, tw);
+        ntt_fwd_middle<N, TH>(dig, L2, tw);
         // (3) last forward stage (pairs 2j, 2j+1), pointwise product with
         // the key row summed over the 2l digit polynomials, and the first
         // inverse stage (the same pairs)
         const uint64_t *row = bsk_ntt + (size_t)i * L2 * 2 * N;
-        for (int j = threadIdx.x; j < N / 2; j += NTT_THREADS) {
+        for (int j = threadIdx.x; j < N / 2; j += TH) {
             const uint64_t S = tw[N / 2 + j];
             uint64_t s0[2] = {0, 0}, s1[2] = {0, 0};
             for (int r = 0; r < L2; ++r) {
@@ -328,12 +337,12 @@ __global__ __launch_bounds__(NTT_THREADS) void k_bootstrap_ntt(
         }
         __syncthreads();
         // (4) inverse stages 1 .. log2 N - 1, the last pass adding into ACC
-        ntt_inv_to_acc<N>(res, twi, acc);
+        ntt_inv_to_acc<N, TH>(res, twi, acc);
     }
 
     // sample extraction of coefficient 0
     uint32_t *o = out + (size_t)g * (N + 1);
-    for (int j = threadIdx.x; j <= N; j += NTT_THREADS) {
+    for (int j = threadIdx.x; j <= N; j += TH) {
         uint32_t v;
         if (j == 0)
             v = acc[0];
@@ -423,7 +432,7 @@ static int launch_bs_ntt(const Ctx *c, const uint32_t *in,
             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
         attr_done = true;
     }
-    hipLaunchKernelGGL(k_bootstrap_ntt<N>, dim3(B), dim3(NTT_THREADS), smem,
+    hipLaunchKernelGGL(k_bootstrap_ntt<N>, dim3(B), dim3(bs_threads(N)), smem,
                        s, c->bsk_ntt, c->tw_fwd, c->tw_inv, in, testv,
                        out, B, d_count, sh.n, sh.beta, sh.l);
     CGGI_HIP_TRY(hipGetLastError());
