@@ -39,8 +39,9 @@
 // LDS holds the accumulators, the digit operands (both signs), the step's
 // key windows in four byte-shifted copies (so every lane reads its 16-byte
 // Toeplitz row as four aligned dwords), double-buffered per digit
-// polynomial, and the modulus-switched inputs.  N = 2048 runs 4 waves per
-// bootstrap (all four limbs per wave) with single-buffered windows.
+// polynomial, and the modulus-switched inputs.  N = 2048 runs 8 waves per
+// bootstrap (all four limbs per wave, a quarter of the block offsets each)
+// with single-buffered windows.
 #include "internal.hpp"
 
 namespace cggi {
@@ -55,9 +56,10 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // computes one output component and two of the four key limbs for all four
 // tiles over half of the block offsets (4 x 2 accumulators).
 // N = 2048: a bootstrap spans 2 column tiles; a workgroup owns one
-// bootstrap, runs 4 waves and single-buffers the (twice as long) windows; a
-// wave computes one output component and all four limbs for both tiles over
-// half of the block offsets (2 x 4 accumulators).
+// bootstrap, runs 8 waves (two per SIMD; 4% faster than one per SIMD with
+// twice the block offsets each) and single-buffers the (twice as long)
+// windows; a wave computes one output component and all four limbs for both
+// tiles over a quarter of the block offsets (2 x 4 accumulators).
 // T (N <= 1024) is the number of column tiles per workgroup: 4 for wide
 // batches; 2 or 1 for narrow ones, so that a batch of few bootstraps spreads
 // over more CUs and each workgroup's step does less work.
@@ -68,7 +70,7 @@ template <int N, int T = 4> struct I8Cfg {
     static constexpr int GPT = BIG ? 1 : 1024 / N;  // bootstraps per column tile
     static constexpr int TILES = BIG ? 2 : T;       // column tiles per workgroup
     static constexpr int GPW = BIG ? TILES / TPG : TILES * GPT; // bootstraps
-    static constexpr int THREADS = BIG ? 256 : 512;
+    static constexpr int THREADS = 512;
     static constexpr int LPW = BIG ? 4 : 2;    // key limbs per wave
     static constexpr int WT = TILES;           // column tiles per wave
     static constexpr int EBUF = BIG ? 1 : 2;   // key-window buffers
@@ -352,7 +354,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     constexpr int WT = C::WT, LPW = C::LPW;
     const int cp = wave & 1;                              // output component
     const int q0 = BIG ? 0 : LPW * ((wave >> 1) & 1);     // first key limb
-    const int half = BIG ? wave >> 1 : wave >> 2;         // block-offset half
+    const int half = BIG ? wave >> 1 : wave >> 2;  // block-offset half (quarter at BIG)
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
@@ -429,7 +431,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
                 }
             };
-            constexpr int ND = NB / 2;    // block offsets per wave
+            constexpr int ND = BIG ? NB / 4 : NB / 2;  // block offsets per wave
             constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
             // this wave's block offsets: dl0 .. dl0 + ND - 1.  Group d0
             // reads the operands of d0 + 1 into the other register buffer
@@ -1006,6 +1008,37 @@ int int8_split_reset(Ctx *c)
     return CGGI_OK;
 }
 
+// The dynamic-LDS limit of the throughput kernels is raised when a context
+// is made (on its device), not at launch: the attribute belongs to the
+// kernel on a device, so launches, also under graph capture, need nothing.
+template <int N, int L, int S>
+static int int8_attrs_ls()
+{
+    const void *fns[3] = {
+        reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S, 4>),
+        nullptr, nullptr};
+    if constexpr (N <= 1024) {
+        fns[1] = reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S, 2>);
+        fns[2] = reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S, 1>);
+    }
+    for (const void *fn : fns)
+        if (fn)
+            CGGI_HIP_TRY(hipFuncSetAttribute(
+                fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    return CGGI_OK;
+}
+
+template <int N>
+static int int8_attrs(const Shape &sh)
+{
+    // the same specialisations launch_bs_int8 picks
+    if (sh.l == 3 && sh.S == 1)
+        return int8_attrs_ls<N, 3, 1>();
+    if (sh.l == 2 && sh.S == 2)
+        return int8_attrs_ls<N, 2, 2>();
+    return int8_attrs_ls<N, 0, 0>();
+}
+
 template <int N>
 static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
 {
@@ -1021,7 +1054,10 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
                        c->bsk_i8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
-    int rc = split_setup<N>(c, s);
+    int rc = int8_attrs<N>(sh);
+    if (rc)
+        return rc;
+    rc = split_setup<N>(c, s);
     if (rc)
         return rc;
     constexpr int64_t ANY = (int64_t)1 << 40;
@@ -1104,13 +1140,6 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     using C = I8Cfg<N, T>;
     const Shape &sh = c->sh;
     size_t smem = I8Smem<N, T>::total(sh.R, sh.n);
-    static bool attr_done = false;
-    if (!attr_done) {
-        CGGI_HIP_TRY(hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_bootstrap_int8<N, L, S, T>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_done = true;
-    }
     int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8<N, L, S, T>), dim3(grid),
                        dim3(C::THREADS), smem, s, c->bsk_i8, in,

@@ -415,6 +415,18 @@ int ntt_transform_bsk(Ctx *c, const uint32_t *bsk, hipStream_t s)
         return set_error(CGGI_E_PARAM, "NTT form: unsupported N");
     }
     CGGI_HIP_TRY(hipGetLastError());
+    // the bootstrap kernel's dynamic-LDS limit, set when a context is made
+    // (on its device) so that launches, also under graph capture, need
+    // nothing
+    const void *fn = nullptr;
+    switch (sh.N) {
+    case 256: fn = reinterpret_cast<const void *>(&k_bootstrap_ntt<256>); break;
+    case 512: fn = reinterpret_cast<const void *>(&k_bootstrap_ntt<512>); break;
+    case 1024: fn = reinterpret_cast<const void *>(&k_bootstrap_ntt<1024>); break;
+    default: fn = reinterpret_cast<const void *>(&k_bootstrap_ntt<2048>); break;
+    }
+    CGGI_HIP_TRY(hipFuncSetAttribute(
+        fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     return CGGI_OK;
 }
 
@@ -425,13 +437,6 @@ static int launch_bs_ntt(const Ctx *c, const uint32_t *in,
 {
     const Shape &sh = c->sh;
     size_t smem = ntt_smem<N>(sh.n, sh.l);
-    static bool attr_done = false;
-    if (!attr_done) {
-        CGGI_HIP_TRY(hipFuncSetAttribute(
-            reinterpret_cast<const void *>(&k_bootstrap_ntt<N>),
-            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_done = true;
-    }
     hipLaunchKernelGGL(k_bootstrap_ntt<N>, dim3(B), dim3(bs_threads(N)), smem,
                        s, c->bsk_ntt, c->tw_fwd, c->tw_inv, in, testv,
                        out, B, d_count, sh.n, sh.beta, sh.l);
