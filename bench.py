@@ -7,7 +7,10 @@ one cggi_eval_level call over that level: linear pre-op, modulus switch,
 accumulator init, 630 CMux steps, sample extraction and key switch for every
 gate, writing the 1024 output wires.  Inputs and keys are resident in HBM
 before timing starts.  The int8-MFMA form gives `value`; the NTT form is
-timed on the same batch and reported beside it.
+timed on the same batch and reported beside it.  Each form's step is also
+captured once as a HIP graph and replayed `steps` times (`graph_replay`:
+mean and median per replay, and whether the replays reproduce the eager
+outputs).
 
 Keys and ciphertexts are seeded uniform arrays: real ones are
 indistinguishable from uniform under the LWE assumption and every kernel's
@@ -198,6 +201,34 @@ def main():
         res[form] = dict(ms_per_step=ms, bs_kernel_ms=bs_ms / max(bs_n, 1),
                          ks_kernel_ms=ks_ms / max(ks_n, 1),
                          bootstraps_per_s=G * 1000.0 / ms)
+        # the same step captured once as a HIP graph: one warm-up replay,
+        # then `steps` replays, each bracketed by events on the replay
+        # stream (mean and median reported beside the eager steps above)
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            ctx.eval_level(form, gates, wires)
+        graph.replay()
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True)
+               for _ in range(args.steps + 1)]
+        evs[0].record(stream)
+        for k in range(args.steps):
+            graph.replay()
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        per = sorted(evs[k].elapsed_time(evs[k + 1])
+                     for k in range(args.steps))
+        gms = evs[0].elapsed_time(evs[-1]) / args.steps
+        same = np.array_equal(cggi.to_host(wires[2 * G:]), outs[form])
+        del graph
+        res[form]["graph"] = dict(
+            replays=args.steps, ms_per_step=round(gms, 4),
+            median_ms=round(per[len(per) // 2], 4),
+            bootstraps_per_s=round(G * 1000.0 / gms, 1),
+            outputs_equal_eager=bool(same))
         log(f"[bench] form={form}: {ms:.3f} ms/step, bootstrap kernel "
             f"{res[form]['bs_kernel_ms']:.3f} ms, key switch "
             f"{res[form]['ks_kernel_ms']:.3f} ms")
@@ -256,6 +287,7 @@ def main():
                    "form": main_form, "batch": G, "gates_per_step": G,
                    "bootstraps_per_step": G},
         "roofline": roof,
+        "graph_replay": res[main_form]["graph"],
     }
     if "ntt" in res and main_form != "ntt":
         rn = res["ntt"]
@@ -264,6 +296,7 @@ def main():
         line["ntt_form"] = {
             "value": round(rn["bootstraps_per_s"], 1),
             "ms_per_step": round(rn["ms_per_step"], 4),
+            "graph_replay": rn["graph"],
             "roofline": {"bound": "alu", "achieved": round(ach, 3),
                          "peak": PEAK_MULMOD_T, "unit": "Tmulmod/s",
                          "frac": round(ach / PEAK_MULMOD_T, 4),
