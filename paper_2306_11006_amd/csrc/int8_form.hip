@@ -62,7 +62,9 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 // tiles over a quarter of the block offsets (2 x 4 accumulators).
 // T (N <= 1024) is the number of column tiles per workgroup: 4 for wide
 // batches; 2 or 1 for narrow ones, so that a batch of few bootstraps spreads
-// over more CUs and each workgroup's step does less work.
+// over more CUs and each workgroup's step does less work.  With one tile a
+// workgroup runs 16 waves (four per SIMD), each over a quarter of the block
+// offsets, to cover the latency of its short MFMA groups.
 template <int N, int T = 4> struct I8Cfg {
     static constexpr bool BIG = N > 1024;
     static constexpr int NB = N / 32;          // blocks per polynomial
@@ -70,7 +72,9 @@ template <int N, int T = 4> struct I8Cfg {
     static constexpr int GPT = BIG ? 1 : 1024 / N;  // bootstraps per column tile
     static constexpr int TILES = BIG ? 2 : T;       // column tiles per workgroup
     static constexpr int GPW = BIG ? TILES / TPG : TILES * GPT; // bootstraps
-    static constexpr int THREADS = 512;
+    // one tile per workgroup: 16 waves, each over a quarter of the block
+    // offsets (17% faster per level than 8 waves; two tiles would spill)
+    static constexpr int THREADS = (!BIG && T == 1) ? 1024 : 512;
     static constexpr int LPW = BIG ? 4 : 2;    // key limbs per wave
     static constexpr int WT = TILES;           // column tiles per wave
     static constexpr int EBUF = BIG ? 1 : 2;   // key-window buffers
@@ -354,7 +358,8 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     constexpr int WT = C::WT, LPW = C::LPW;
     const int cp = wave & 1;                              // output component
     const int q0 = BIG ? 0 : LPW * ((wave >> 1) & 1);     // first key limb
-    const int half = BIG ? wave >> 1 : wave >> 2;  // block-offset half (quarter at BIG)
+    // block-offset part: half, or quarter at N = 2048 and with 16 waves
+    const int half = BIG ? wave >> 1 : wave >> 2;
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
@@ -431,7 +436,9 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                     bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
                 }
             };
-            constexpr int ND = BIG ? NB / 4 : NB / 2;  // block offsets per wave
+            // block offsets per wave: NB over the waves that share a
+            // (component, limb set)
+            constexpr int ND = BIG ? NB / 4 : NB / (I8_THREADS / 256);
             constexpr int STASH0 = ND >= PER_T + 4 ? 4 : 0;
             // this wave's block offsets: dl0 .. dl0 + ND - 1.  Group d0
             // reads the operands of d0 + 1 into the other register buffer
