@@ -208,10 +208,11 @@ int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
  * for at most half as many tiles, on eight (each block's four key limbs in
  * two pairs), or, for up to twice as many tiles, on two (one per output
  * component), which exchange their partial products after every CMux step
- * through device memory.  Results are bit-identical to the one-workgroup kernel.  Every
- * INT8 call picks its kernel from the batch size: latency mode with eight,
- * four, then two workgroups per tile while the tiles fit, then one
- * workgroup per 1, 2 or 4 tiles (or as cggi_ctx_int8_plan sets).  cggi_bootstrap_batch decides on the host from B;
+ * through device memory.  Results are bit-identical to the one-workgroup
+ * kernel.  Every INT8 call picks its kernel from the batch size: latency
+ * mode with eight, four, then two workgroups per tile while the tiles fit,
+ * then one workgroup per 1, 2 or 4 tiles (or as cggi_ctx_int8_plan sets).
+ * cggi_bootstrap_batch decides on the host from B;
  * cggi_eval_level, whose bootstrap count is known only on the device,
  * launches every candidate up to the one that holds 2G bootstraps, and each
  * runs only if the device count falls in its range.  cggi_ctx_latency_groups
