@@ -322,11 +322,16 @@ def main():
             ctx.profile(False)
             narrow[mode] = round(bms / max(bn, 1), 3)
         ctx.latency_mode(True)
-        ctx.check()
-        line["narrow_level"] = dict(
-            bootstraps=1, **narrow,
-            kernels=["k_bootstrap_int8_split<1024, 3, 1, 8>",
-                     "k_bootstrap_int8<1024, 3, 1, 1>"])
+        try:
+            ctx.check()
+            line["narrow_level"] = dict(
+                bootstraps=1, **narrow,
+                kernels=["k_bootstrap_int8_split<1024, 3, 1, 8>",
+                         "k_bootstrap_int8<1024, 3, 1, 1>"])
+        except cggi.CggiError as e:
+            # a latency-mode wait timed out (e.g. CUs taken by another
+            # process): the figures above are void, the main line stands
+            line["narrow_level"] = {"error": str(e)}
     line["kernel_ms"] = {f: {"bootstrap": round(v["bs_kernel_ms"], 4),
                              "keyswitch": round(v["ks_kernel_ms"], 4)}
                          for f, v in res.items()}
