@@ -115,6 +115,7 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_fwd);
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
+    (void)hipFree(c->corr_i8);
     for (int v = 0; v < 3; ++v) {
         (void)hipFree(c->x_buf[v]);
         (void)hipFree(c->x_epoch[v]);

@@ -22,9 +22,14 @@
 //    and are recombined mod 2^32.
 //  * Digits.  Gadget digits in [-Bg/2, Bg/2) are split into 7-bit
 //    sub-digits delta in [-64, 64) (one for Bg <= 2^7); delta and its
-//    negation (for wrapped blocks) both fit int8.
-//  * Exactness: |sum| <= R*N*64*128 < 2^31, so int32 never overflows, and
-//    the recombination is a ring identity mod 2^32.
+//    negation (for wrapped blocks) both fit int8.  The wide kernel stores
+//    delta + 64 and 63 - delta instead (both in [0, 127]: non-negative
+//    operands take the matrix cores less energy) and starts one accumulator
+//    per output coefficient from minus the offsets' contribution, which
+//    depends on the key only and is tabulated once per context.
+//  * Exactness: |sum| <= R*N*128*128 < 2^31 for every parameter set the
+//    context accepts, and int32 MFMA accumulation wraps mod 2^32 in any
+//    case, so the recombination mod 2^32 is exact.
 //
 // Launch layout (N <= 1024): 512 threads (8 waves, two per SIMD) per
 // workgroup, one workgroup per CU (LDS-limited); a workgroup owns 4 column
@@ -145,6 +150,71 @@ __global__ void k_int8_key(const uint32_t *__restrict__ bsk,
     }
 }
 
+// Offset correction of the digit operands (decompose_acc with OFF).  With
+// the positive copy holding delta + 64 and the negated copy 63 - delta, the
+// GEMM output for coefficient j = 32J + rho of component c' at step i
+// exceeds the product by
+//   sum over digit rows of (64 * sum_{Delta <= J} W_Delta[rho]
+//                           + 63 * sum_{Delta > J} W_Delta[rho])
+//   = sum over digit rows of (63 * total[rho] + head_J[rho]),
+// where W_Delta[rho] = sum_{kappa < 32} a_ext[32 Delta + rho - kappa] *
+// 2^(7s) is the row sum of the Toeplitz block A_Delta of that row's key
+// polynomial, total[rho] the sum over every Delta and head_J[rho] the sum
+// over Delta <= J (block offsets up to J use the positive copy).  corr
+// [n][2][N] holds that excess mod 2^32; the bootstrap kernel starts one
+// accumulator per output coefficient from its negation.  One workgroup per
+// (i, c').
+template <int N>
+__global__ __launch_bounds__(256) void k_int8_corr(
+    const uint32_t *__restrict__ bsk, uint32_t *__restrict__ corr, int n,
+    int l, int S)
+{
+    constexpr int NB = N / 32, PT = N / 256;
+    __shared__ uint32_t ext[N + 32];   // ext[x + 31] = a_ext[x], -31 <= x < N
+    __shared__ uint32_t W[N];          // W_Delta[rho] at 32 Delta + rho
+    const int i = blockIdx.x >> 1, cp = blockIdx.x & 1;
+    if (i >= n)
+        return;
+    const int tid = threadIdx.x;
+    const int R = 2 * l * S;
+    uint32_t accv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        accv[k] = 0u;
+    for (int kb = 0; kb < R; ++kb) {
+        const int r = kb / S, s = kb - r * S;
+        const uint32_t *a = bsk + (((size_t)i * 2 * l + r) * 2 + cp) * N;
+        for (int x = tid - 31; x < N; x += 256)
+            ext[x + 31] = x >= 0 ? a[x] : 0u - a[x + N];
+        __syncthreads();
+        for (int t = tid; t < N; t += 256) {
+            uint32_t w = 0;
+            for (int kap = 0; kap < 32; ++kap)
+                w += ext[t - kap + 31];
+            W[t] = w;
+        }
+        __syncthreads();
+        if (tid < 32) {                // prefix over Delta, per rho
+            uint32_t run = 0;
+            for (int D = 0; D < NB; ++D) {
+                run += W[32 * D + tid];
+                W[32 * D + tid] = run;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int j = tid + 256 * k, J = j >> 5, rho = j & 31;
+            const uint32_t total = W[32 * (NB - 1) + rho];
+            accv[k] += (63u * total + W[32 * J + rho]) << (7 * s);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        corr[((size_t)i * 2 + cp) * N + tid + 256 * k] = accv[k];
+}
+
 template <int N, int T = 4>
 struct I8Smem {
     using C = I8Cfg<N, T>;
@@ -163,7 +233,13 @@ struct I8Smem {
 // bytes of each lane's B operand hold one 32-block's kappa in reverse.
 // NC = 1 decomposes component c_sel only, into rows 0 .. l*SS - 1 (R then
 // counts the rows per bootstrap of that layout).
-template <int N, int L, int S, int GPW, int THREADS, int NC = 2>
+// OFF stores each sub-digit delta as delta + 64 and its negation as
+// 63 - delta, both in [0, 127]: non-negative operands cost the matrix cores
+// less energy (4-5% faster at the power limit).  The offsets' contribution,
+// a function of the key alone, is removed with a precomputed table (see
+// k_int8_corr).
+template <int N, int L, int S, int GPW, int THREADS, int NC = 2,
+          bool OFF = false>
 __device__ __forceinline__ void decompose_acc(
     const uint32_t *acc, int8_t *dig, const uint16_t *ms, int i, int n, int l,
     int SS, int R, int beta, uint32_t dig_off, uint32_t bmask, int32_t bhalf,
@@ -204,7 +280,7 @@ __device__ __forceinline__ void decompose_acc(
             for (int s = 0; s < (L ? S : 2); ++s) {
                 if (!L && s >= SS)
                     break;
-                uint32_t pos = 0;
+                uint32_t pos = 0, neg = 0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     int32_t sd;
@@ -214,13 +290,20 @@ __device__ __forceinline__ void decompose_acc(
                         sd = ((d[k] + 64) & 127) - 64;
                         d[k] = (d[k] - sd) >> 7;
                     }
-                    pos |= ((uint32_t)sd & 0xFFu) << (8 * (3 - k));
+                    if (OFF) {
+                        pos |= (uint32_t)(sd + 64) << (8 * (3 - k));
+                        neg |= (uint32_t)(63 - sd) << (8 * (3 - k));
+                    } else {
+                        pos |= ((uint32_t)sd & 0xFFu) << (8 * (3 - k));
+                    }
                 }
-                // negate the four bytes at once: ~b + 1 per byte, the
-                // +1 kept inside each byte's low 7 bits
-                const uint32_t npos = ~pos;
-                uint32_t neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
-                               (npos & 0x80808080u);
+                if (!OFF) {
+                    // negate the four bytes at once: ~b + 1 per byte, the
+                    // +1 kept inside each byte's low 7 bits
+                    const uint32_t npos = ~pos;
+                    neg = ((npos & 0x7F7F7F7Fu) + 0x01010101u) ^
+                          (npos & 0x80808080u);
+                }
                 int kb = ((NC == 2 ? c * l : 0) + (p - 1)) * SS + s;
                 int8_t *base = gbase + (size_t)kb * 2 * N;
                 *reinterpret_cast<uint32_t *>(base) = pos;
@@ -235,7 +318,7 @@ __device__ __forceinline__ void decompose_acc(
 // run time.
 template <int N, int L, int S, int T>
 __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
-    const int8_t *__restrict__ key,
+    const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
     uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
     int lo, int hi, int n, int beta, int l_rt, int S_rt)
@@ -244,6 +327,11 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
     constexpr int EBUF = C::EBUF;
     constexpr bool BIG = C::BIG;
+    // offset digits (non-negative operands, which the power-bound wide
+    // kernel runs faster on) with the key-only correction; the latency-bound
+    // one- and two-tile kernels gain nothing from it and the N = 2048 layout
+    // has no registers to spare, so they keep signed digits
+    constexpr bool OFF = !BIG && T == 4;
     constexpr int I8_THREADS = C::THREADS;
     constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW, AST = C::AST;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
@@ -360,6 +448,8 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     const int q0 = BIG ? 0 : LPW * ((wave >> 1) & 1);     // first key limb
     // block-offset part: half, or quarter at N = 2048 and with 16 waves
     const int half = BIG ? wave >> 1 : wave >> 2;
+    // the wave that adds the offset correction of its output component
+    const bool corr_wave = half == 0 && q0 == 0;
     const int rho = lane & 31, hh = lane >> 5;
     // A operand: dword offset of this lane inside one (buf, c', q) group
     const int a_lane = (rho & 3) * CLEN + (rho >> 2) + 4 * hh;
@@ -384,9 +474,23 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     for (int i = 0; i < n; ++i) {
         lds_barrier();   // ACC of the previous step complete
         // ---- rotate, subtract, decompose into digit operands --------------
-        decompose_acc<N, L, S, GPW, I8_THREADS>(acc, dig, ms, i, n, l, SS, R,
-                                                beta, dig_off, bmask, bhalf,
-                                                tid);
+        // one wave per output component starts its limb-0 accumulators
+        // from minus the step's offset correction (the same for every tile:
+        // output block Jt[t] depends on the lane only)
+        v16i cinit = {};
+        if (OFF && corr_wave) {
+            const uint32_t *cr =
+                corr + ((size_t)i * 2 + cp) * N + 32 * Jt[0] + 4 * hh;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const v4i c4 = *reinterpret_cast<const v4i *>(cr + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    cinit[4 * g + e] = -c4[e];
+            }
+        }
+        decompose_acc<N, L, S, GPW, I8_THREADS, 2, OFF>(
+            acc, dig, ms, i, n, l, SS, R, beta, dig_off, bmask, bhalf, tid);
         lds_barrier();
 
         // ---- K loop: digit polynomials x block offsets --------------------
@@ -457,7 +561,8 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
 #pragma unroll
                     for (int q = 0; q < LPW; ++q)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[b][q], bf[b][t], zero_start ? zero : Cacc[t][q],
+                            af[b][q], bf[b][t],
+                            zero_start ? (q == 0 ? cinit : zero) : Cacc[t][q],
                             0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < WT * LPW; ++k) {
@@ -1061,6 +1166,18 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     hipLaunchKernelGGL(k_int8_key<N>, dim3(blocks), dim3(256), 0, s, bsk,
                        c->bsk_i8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
+    if (N <= 1024) {
+        // offset correction of the throughput kernels' digit operands
+        size_t cbytes = (size_t)sh.n * 2 * N * sizeof(uint32_t);
+        if (hipMalloc(&c->corr_i8, cbytes) != hipSuccess) {
+            c->corr_i8 = nullptr;
+            return set_error(CGGI_E_NOMEM,
+                             "hipMalloc of the int8 offset correction failed");
+        }
+        hipLaunchKernelGGL(k_int8_corr<N>, dim3(2 * sh.n), dim3(256), 0, s,
+                           bsk, c->corr_i8, sh.n, sh.l, sh.S);
+        CGGI_HIP_TRY(hipGetLastError());
+    }
     int rc = int8_attrs<N>(sh);
     if (rc)
         return rc;
@@ -1149,7 +1266,7 @@ static int launch_bs_int8_t(const Ctx *c, const uint32_t *in,
     size_t smem = I8Smem<N, T>::total(sh.R, sh.n);
     int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8<N, L, S, T>), dim3(grid),
-                       dim3(C::THREADS), smem, s, c->bsk_i8, in,
+                       dim3(C::THREADS), smem, s, c->bsk_i8, c->corr_i8, in,
                        testv, out, B, d_count, lo, hi, sh.n, sh.beta, sh.l,
                        sh.S);
     CGGI_HIP_TRY(hipGetLastError());

@@ -38,6 +38,7 @@ struct cggi_ctx {
     uint64_t *tw_inv = nullptr;   // [N] psi^-bitrev(i)
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
+    uint32_t *corr_i8 = nullptr;  // [n][2][N] digit-offset correction (N <= 1024)
     // INT8 latency mode (one tile over G = 8, 4 or 2 workgroups, N <= 1024);
     // index 0: G = 4, index 1: G = 2, index 2: G = 8
     bool split_on = true;         // cggi_ctx_latency_mode
