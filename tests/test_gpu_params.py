@@ -1,9 +1,10 @@
 """Parameter sets beyond the three named ones: ring degree 512, digit widths
 that take the int8 form's generic (run-time l, S) kernel and its 7-bit
 sub-digit split, and key-switch bases from 2^1 to 2^4 (int8 GEMM key
-switch) and 2^5 (row-gather key switch).  Both forms and the
-key switch are compared with the oracle coefficient by coefficient on
-uniform keys, for one full workgroup of bootstraps plus a ragged tail."""
+switch) and 2^5 (row-gather key switch).  Both forms (the int8 form under
+its built-in plan and with each throughput kernel forced) and the key
+switch are compared with the oracle coefficient by coefficient on uniform
+keys, for one full four-tile workgroup of bootstraps plus a ragged tail."""
 import concurrent.futures as cf
 import os
 import sys
@@ -70,6 +71,19 @@ def test_params_bootstrap_and_keyswitch_bit_exact(O, p):
         out = ctx.bootstrap(form, x)
         torch.cuda.synchronize()
         assert np.array_equal(cggi.to_host(out), want), (p.name, form)
+    # the built-in plan sends this batch to latency mode; every throughput
+    # kernel (one, two and four tiles per workgroup; the four-tile one with
+    # offset digit operands) on the same full workgroup + ragged tail
+    limits = ctx.int8_limits()
+    for kind in ("tiles1", "tiles2", "tiles4"):
+        if limits[kind] < B:
+            continue
+        say(f"params {p.name} int8 kernel {kind} B={B}")
+        ctx.int8_plan([(kind, 2**31 - 1)])
+        out = ctx.bootstrap("int8", x)
+        torch.cuda.synchronize()
+        assert np.array_equal(cggi.to_host(out), want), (p.name, kind)
+    ctx.int8_plan(None)
     say(f"params {p.name} key switch B={B}")
     ks = ctx.keyswitch(cggi.to_device(want))
     torch.cuda.synchronize()
