@@ -49,6 +49,8 @@
 // with single-buffered windows.
 #include "internal.hpp"
 
+#include <type_traits>
+
 namespace cggi {
 
 namespace {
@@ -494,7 +496,11 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
         lds_barrier();
 
         // ---- K loop: digit polynomials x block offsets --------------------
-        for (int kb = 0; kb < R; ++kb) {
+        // one stage per digit polynomial; the first is a separate
+        // instantiation so that the correction start values (cinit) are
+        // dead in the others
+        auto stage = [&](const int kb, auto first_c) {
+            constexpr bool FIRST = decltype(first_c)::value;
             const int st = i * R + kb;
             const bool more = st + 1 < n * R;
             if constexpr (PD == 1) {
@@ -578,10 +584,7 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
             };
             load_a(dl0, af[0]);
             load_b(dl0, bf[0]);
-            if (kb == 0)
-                group(0, 0, true);    // accumulators start from zero
-            else
-                group(0, 0, false);
+            group(0, 0, FIRST);   // the first stage starts the accumulators
 #pragma unroll 1
             for (int d0 = 1; d0 + 1 < ND; d0 += 2) {
                 group(d0, 1, false);
@@ -601,7 +604,10 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                     stash_one(0, k);
                 lds_barrier();
             }
-        }
+        };
+        stage(0, std::true_type{});
+        for (int kb = 1; kb < R; ++kb)
+            stage(kb, std::false_type{});
 
         // ---- fold limbs, add into ACC ---------------------------------------
 #pragma unroll
