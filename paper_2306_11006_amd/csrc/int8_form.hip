@@ -22,11 +22,12 @@
 //    and are recombined mod 2^32.
 //  * Digits.  Gadget digits in [-Bg/2, Bg/2) are split into 7-bit
 //    sub-digits delta in [-64, 64) (one for Bg <= 2^7); delta and its
-//    negation (for wrapped blocks) both fit int8.  The wide kernel stores
-//    delta + 64 and 63 - delta instead (both in [0, 127]: non-negative
-//    operands take the matrix cores less energy) and starts one accumulator
-//    per output coefficient from minus the offsets' contribution, which
-//    depends on the key only and is tabulated once per context.
+//    negation (for wrapped blocks) both fit int8.  The two- and four-tile
+//    kernels store delta + 64 and 63 - delta instead (both in [0, 127]:
+//    non-negative operands take the matrix cores less energy) and start one
+//    accumulator per output coefficient from minus the offsets'
+//    contribution, which depends on the key only and is tabulated once per
+//    context.
 //  * Exactness: |sum| <= R*N*128*128 < 2^31 for every parameter set the
 //    context accepts, and int32 MFMA accumulation wraps mod 2^32 in any
 //    case, so the recombination mod 2^32 is exact.
@@ -329,11 +330,11 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
     constexpr int NB = C::NB, GPT = C::GPT, GPW = C::GPW, TPG = C::TPG;
     constexpr int EBUF = C::EBUF;
     constexpr bool BIG = C::BIG;
-    // offset digits (non-negative operands, which the power-bound wide
-    // kernel runs faster on) with the key-only correction; the latency-bound
-    // one- and two-tile kernels gain nothing from it and the N = 2048 layout
-    // has no registers to spare, so they keep signed digits
-    constexpr bool OFF = !BIG && T == 4;
+    // offset digits (non-negative operands, which the matrix cores run
+    // faster on when the CUs are all busy) with the key-only correction; the
+    // latency-bound one-tile kernel gains nothing from it and the N = 2048
+    // layout has no registers to spare, so they keep signed digits
+    constexpr bool OFF = !BIG && T >= 2;
     constexpr int I8_THREADS = C::THREADS;
     constexpr int CLEN = C::CLEN, CW = C::CW, EW = C::EW, AST = C::AST;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
