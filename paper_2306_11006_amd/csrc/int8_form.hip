@@ -563,14 +563,28 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                     load_b(dl0 + d0 + 1, bf[b ^ 1]);
                 }
                 const v16i zero = {};
+                auto mfma = [&](int t, int q) {
+                    Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                        af[b][q], bf[b][t],
+                        zero_start ? (q == 0 ? cinit : zero) : Cacc[t][q],
+                        0, 0, 0);
+                };
+                // tile-outer order for four tiles, limb-outer for two (each
+                // 1-2% faster than the other order on the MI355X; the sums
+                // do not depend on it)
+                if constexpr (T == 4) {
 #pragma unroll
-                for (int t = 0; t < WT; ++t)
+                    for (int t = 0; t < WT; ++t)
+#pragma unroll
+                        for (int q = 0; q < LPW; ++q)
+                            mfma(t, q);
+                } else {
 #pragma unroll
                     for (int q = 0; q < LPW; ++q)
-                        Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[b][q], bf[b][t],
-                            zero_start ? (q == 0 ? cinit : zero) : Cacc[t][q],
-                            0, 0, 0);
+#pragma unroll
+                        for (int t = 0; t < WT; ++t)
+                            mfma(t, q);
+                }
 #pragma unroll
                 for (int k = 0; k < WT * LPW; ++k) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
