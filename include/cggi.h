@@ -93,8 +93,9 @@ int cggi_params_check(const cggi_params_t *params);
  * bitmask of cggi_form_t): the NTT form stores the bootstrapping key
  * transformed mod Q (8 * n*2l*2*N bytes), the INT8 form stores its int8
  * limb windows (n*R*2*4*(N+64) bytes, R = 2l digit rows for Bg <= 2^7,
- * 4l for Bg <= 2^13).  For key-switch bases up to 2^4 the context also
- * stores d_ksk as int8 limb blocks for the GEMM key switch
+ * 4l for Bg <= 2^13) and, for N <= 1024, the key-only correction of its
+ * offset digit operands (4 * n*2*N bytes).  For key-switch bases up to 2^4
+ * the context also stores d_ksk as int8 limb blocks for the GEMM key switch
  * (ceil((n+1)/32) * N * ceil(t*2^gamma/32) * 4 KB).  d_bsk may be freed
  * once this call returns (it synchronises `stream`).  d_ksk
  * ([N][t][2^gamma][n+1]) must stay valid and unchanged for the context's
