@@ -51,13 +51,14 @@ unsigned bitrev(unsigned x, int bits)
 // covers three stages.
 // NS Cooley-Tukey stages on the 2^NS elements of one block held in
 // registers: the block starts in group i of stage s0 (m0 = 2^s0 groups).
-template <int NS>
+// U0 > 0 starts at that stage (the earlier ones done by the caller).
+template <int NS, int U0 = 0>
 __device__ __forceinline__ void fwd_block(uint64_t (&v)[1 << NS], int m0, int i,
                                           const uint64_t *__restrict__ tw)
 {
     constexpr int K = 1 << NS;
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
+    for (int u = U0; u < NS; ++u) {
         const int d = 1 << (NS - 1 - u);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -277,6 +278,10 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
         dig_off += (1u << (beta - 1)) << (32 - p * beta);
     const uint32_t bmask = (1u << beta) - 1u;
     const int32_t bhalf = 1 << (beta - 1);
+    // psi^(N/2) is a primitive 4th root of unity: 2^48 or Q - 2^48 (checked
+    // when the tables are made)
+    const bool w4_neg = tw[1] != (uint64_t(1) << 48);
+    const bool small_digits = beta <= 14;
 
     for (int i = 0; i < n; ++i) {
         const int e = ms[i];
@@ -299,11 +304,32 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
             }
             for (int p = 1; p <= l; ++p) {
                 uint64_t v[8];
+                int32_t dg[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    v[k] = gl::from_i32(
-                        (int32_t)((w[k] >> (32 - p * beta)) & bmask) - bhalf);
-                fwd_block<3>(v, 1, 0, tw);
+                    dg[k] = (int32_t)((w[k] >> (32 - p * beta)) & bmask) -
+                            bhalf;
+                if (small_digits) {
+                    // stage 0 in signed integers: its twiddle psi^(N/2) is
+                    // +-2^48 and |digit| <= 2^13, so U +- 2^48 V stays
+                    // below 2^62 and needs no reduction
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        int64_t V = (int64_t)dg[k + 4] * (int64_t(1) << 48);
+                        V = w4_neg ? -V : V;
+                        const int64_t a0 = (int64_t)dg[k] + V;
+                        const int64_t a1 = (int64_t)dg[k] - V;
+                        v[k] = a0 >= 0 ? (uint64_t)a0 : (uint64_t)a0 + gl::Q;
+                        v[k + 4] = a1 >= 0 ? (uint64_t)a1
+                                           : (uint64_t)a1 + gl::Q;
+                    }
+                    fwd_block<3, 1>(v, 1, 0, tw);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        v[k] = gl::from_i32(dg[k]);
+                    fwd_block<3>(v, 1, 0, tw);
+                }
                 uint64_t *x = dig + (size_t)(c * l + p - 1) * N + off;
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
@@ -387,6 +413,9 @@ int ntt_make_tables(Ctx *c, hipStream_t s)
         f[i] = gl::pow_host(psi, r);
         iv[i] = gl::pow_host(psi_inv, r);
     }
+    // the bootstrap kernel does the first forward stage as a shift by 48
+    if (f[1] != (1ull << 48) && f[1] != gl::Q - (1ull << 48))
+        return set_error(CGGI_E_PARAM, "NTT form: psi^(N/2) is not +-2^48");
     CGGI_HIP_TRY(hipMalloc(&c->tw_fwd, N * sizeof(uint64_t)));
     CGGI_HIP_TRY(hipMalloc(&c->tw_inv, N * sizeof(uint64_t)));
     CGGI_HIP_TRY(hipMemcpyAsync(c->tw_fwd, f.data(), N * sizeof(uint64_t),
