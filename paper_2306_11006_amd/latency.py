@@ -1,6 +1,6 @@
 """End-to-end latency of encrypted integer arithmetic on one GPU.
 
-    python -m paper_2306_11006_amd.latency [--op add mul] [--bits 32]
+    python -m paper_2306_11006_amd.latency [--op add mul uneven] [--bits 32]
         [--form int8 ntt] [--reps 5] [--params default]
 
 For every (operation, circuit design, form) it builds the netlist
@@ -27,17 +27,23 @@ import torch
 from . import arith, cggi, inputs, params
 from .circuit import LevelledCircuit
 
-STYLES = {"add": ("ripple", "prefix"), "mul": ("array", "tree")}
+STYLES = {"add": ("ripple", "prefix"), "mul": ("array", "tree"),
+          "uneven": ("ripple+array",)}
 
 
 def build(op, bits, style):
+    """(netlist, input wires, output wires) of one circuit.  "uneven" is the
+    uneven-level workload: a bits-wide ripple-carry adder beside a bits x
+    bits array multiplier (inputs.adder_multiplier_circuit)."""
     if op == "add":
         nl, io = arith.adder(bits, style)
-        outs = io["sum"]
-    else:
+        return nl, list(io["a"]) + list(io["b"]), list(io["sum"])
+    if op == "mul":
         nl, io = arith.multiplier(bits, style)
-        outs = io["prod"]
-    return nl, list(io["a"]) + list(io["b"]), list(outs)
+        return nl, list(io["a"]) + list(io["b"]), list(io["prod"])
+    nl, io = inputs.adder_multiplier_circuit(bits)
+    return (nl, list(io["a"]) + list(io["b"]) + list(io["x"]) +
+            list(io["y"]), list(io["sum"]) + list(io["prod"]))
 
 
 def time_case(ctx, p, form, nl, ins, outs, reps, seed):
@@ -86,7 +92,7 @@ def time_case(ctx, p, form, nl, ins, outs, reps, seed):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--op", nargs="+", default=["add", "mul"],
-                    choices=["add", "mul"])
+                    choices=["add", "mul", "uneven"])
     ap.add_argument("--style", nargs="+", default=None,
                     help="circuit designs (default: all of the operation's)")
     ap.add_argument("--bits", type=int, default=32)

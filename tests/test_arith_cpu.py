@@ -110,3 +110,27 @@ def test_latency_cli_needs_gpu():
     from paper_2306_11006_amd import latency
     with pytest.raises(SystemExit, match="no GPU"):
         latency.main(["--op", "add"])
+
+
+def test_uneven_level_circuit_for_the_latency_cli():
+    """The latency CLI's uneven-level workload: a 16-bit ripple adder beside
+    a 16 x 16 array multiplier, 1455 gates in 88 levels; its input and
+    output wire lists compute a + b and x * y on plaintext bits."""
+    from paper_2306_11006_amd import latency
+    nl, ins, outs = latency.build("uneven", 16, "ripple+array")
+    g = nl.array()
+    order, starts = cggi.levelize(g, nl.n_wires)
+    assert (len(g), len(ins), len(outs), len(starts) - 1) == \
+        (1455, 64, 49, 88)
+    for A, B, X, Y in [(0, 0, 0, 0), (65535, 65535, 65535, 65535),
+                       (12345, 54321, 40000, 333)]:
+        vals = {}
+        for i in range(16):
+            vals[ins[i]] = (A >> i) & 1
+            vals[ins[16 + i]] = (B >> i) & 1
+            vals[ins[32 + i]] = (X >> i) & 1
+            vals[ins[48 + i]] = (Y >> i) & 1
+        v = inputs.eval_plain(g, vals)
+        s = sum(v[w] << i for i, w in enumerate(outs[:17]))
+        p = sum(v[w] << i for i, w in enumerate(outs[17:]))
+        assert (s, p) == (A + B, X * Y)
