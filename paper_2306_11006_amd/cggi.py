@@ -28,6 +28,7 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_reserve", "cggi_bootstrap_batch", "cggi_keyswitch_batch",
            "cggi_eval_level", "cggi_levelize", "cggi_ctx_profile",
            "cggi_ctx_profile_read", "cggi_measure_int8_mfma",
+           "cggi_measure_mulmod",
            "cggi_ctx_latency_mode", "cggi_ctx_latency_groups",
            "cggi_ctx_check", "cggi_ctx_int8_plan", "cggi_ctx_int8_plan_get",
            "cggi_ctx_int8_limits", "cggi_ctx_latency_abort",
@@ -77,6 +78,7 @@ def lib():
         L.cggi_ctx_profile.argtypes = [vp, ctypes.c_int]
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)
         L.cggi_ctx_profile_read.argtypes = [vp, dp, ip, dp, ip]
+        L.cggi_measure_mulmod.argtypes = [i32, dp]
         L.cggi_ctx_latency_mode.argtypes = [vp, i32]
         L.cggi_ctx_latency_groups.argtypes = [vp, ip]
         L.cggi_ctx_check.argtypes = [vp]
@@ -119,6 +121,14 @@ def measure_int8_mfma(iters=40000, random_operands=True):
     return out.value
 
 
+def measure_mulmod(iters=20000):
+    """Tera Goldilocks multiply-mods per second a bare loop of the NTT
+    form's multiply-mod sustains on the current device."""
+    out = ctypes.c_double()
+    _check(lib().cggi_measure_mulmod(int(iters), ctypes.byref(out)))
+    return out.value
+
+
 def levelize(gates, n_wires):
     """Host levelisation (cggi_levelize): returns (order, level_start) as
     numpy int32 arrays; level L is gates[order[level_start[L]:
@@ -147,6 +157,29 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _shape(t, name, *dims):
+    """Raise ValueError unless tensor t has the given shape (None matches
+    any extent).  Checked before any pointer reaches the C ABI, which takes
+    sizes on trust from its arguments."""
+    if t is None:
+        return
+    if t.dim() != len(dims) or any(d is not None and t.shape[i] != d
+                                   for i, d in enumerate(dims)):
+        want = "[" + ", ".join("*" if d is None else str(d)
+                               for d in dims) + "]"
+        raise ValueError(f"{name}: expected shape {want}, got "
+                         f"{list(t.shape)}")
+
+
+def _numel(t, name, shape):
+    n = 1
+    for d in shape:
+        n *= d
+    if t is None or t.numel() != n:
+        raise ValueError(f"{name}: expected {n} elements ({list(shape)}), "
+                         f"got {None if t is None else t.numel()}")
+
+
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -167,6 +200,8 @@ class Context:
         mask = 0
         for f in forms:
             mask |= _form(f)
+        _numel(bsk, "bsk", params.bsk_shape)
+        _numel(ksk, "ksk", params.ksk_shape)
         self._ps = params_struct(params)
         h = ctypes.c_void_p()
         _check(lib().cggi_ctx_create(ctypes.byref(self._ps), _ptr(bsk),
@@ -261,7 +296,11 @@ class Context:
 
     def bootstrap(self, form, inp, out=None, testv=None, stream=None):
         p = self.params
+        _shape(inp, "inp", None, p.n + 1)
         B = inp.shape[0]
+        _shape(out, "out", B, p.N + 1)
+        if testv is not None:
+            _numel(testv, "testv", (p.N,))
         if out is None:
             out = torch.empty((B, p.N + 1), dtype=torch.int32,
                               device=inp.device)
@@ -272,7 +311,9 @@ class Context:
 
     def keyswitch(self, inp, out=None, stream=None):
         p = self.params
+        _shape(inp, "inp", None, p.N + 1)
         B = inp.shape[0]
+        _shape(out, "out", B, p.n + 1)
         if out is None:
             out = torch.empty((B, p.n + 1), dtype=torch.int32,
                               device=inp.device)
@@ -283,11 +324,14 @@ class Context:
     def eval_level(self, form, gates, wires, stream=None):
         """gates: int32 tensor [G, 5] (op, in0, in1, in2, out); wires:
         int32 tensor [W, n+1], updated in place."""
+        _shape(gates, "gates", None, 5)
+        _shape(wires, "wires", None, self.params.n + 1)
         G = gates.shape[0]
         W = wires.shape[0]
         _check(lib().cggi_eval_level(self._h, _form(form), _ptr(gates), G,
                                      _ptr(wires), W, _stream(stream)))
         return wires
+
 
 
 def to_device(a, device="cuda"):

@@ -80,6 +80,9 @@ static int check_form(const Shape &s, uint32_t form)
     if (form & CGGI_FORM_INT8) {
         if (s.S == 0)
             return set_error(CGGI_E_PARAM, "INT8 form: bg_bit must be <= 13");
+        // the generic build's digit loops run over at most 8 gadget levels
+        if (s.l > 8)
+            return set_error(CGGI_E_PARAM, "INT8 form: l must be <= 8");
         if (int8_smem_bytes(s.N, s.R, s.n) > LDS_BYTES)
             return set_error(CGGI_E_PARAM, "INT8 form: workgroup exceeds LDS");
     }
@@ -121,6 +124,8 @@ static void free_ctx(Ctx *c)
         (void)hipFree(c->x_epoch[v]);
     }
     (void)hipFree(c->x_err);
+    if (c->abort_stream)
+        (void)hipStreamDestroy(c->abort_stream);
     (void)hipFree(c->ksk_i8);
     (void)hipFree(c->ws_small);
     (void)hipFree(c->ws_big);
@@ -161,7 +166,7 @@ static int reserve(Ctx *c, int32_t G, hipStream_t s)
 
 ProfScope::ProfScope(Ctx *c, int kind, hipStream_t s) : c_(c), s_(s)
 {
-    if (!c_->prof)
+    if (!c_ || !c_->prof)
         return;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess ||
@@ -189,6 +194,28 @@ static void prof_clear(Ctx *c)
 {
     c->ev_used = 0;
     c->ev_marks.clear();
+}
+
+int level_args_check(Ctx *c, cggi_form_t form, const cggi_gate_t *gates,
+                     int32_t G, uint32_t *wires, int32_t W)
+{
+    if (!c)
+        return set_error(CGGI_E_PARAM, "ctx is NULL");
+    if (form != CGGI_FORM_NTT && form != CGGI_FORM_INT8)
+        return set_error(CGGI_E_PARAM, "unknown form");
+    if (!(c->forms & (uint32_t)form))
+        return set_error(CGGI_E_UNSUPPORTED, "form not built into the context");
+    if (G < 0 || G > (1 << 22) || W < 1 || W > (1 << 26))
+        return set_error(CGGI_E_SHAPE, "need 0 <= G <= 2^22, 1 <= W <= 2^26");
+    if (G == 0)
+        return CGGI_OK;
+    if (!gates || !wires || !aligned4(gates) || !aligned4(wires))
+        return set_error(CGGI_E_SHAPE, "gates/wires must be non-NULL and "
+                                       "4-byte aligned");
+    if (overlap(gates, (size_t)G * sizeof(cggi_gate_t), wires,
+                (size_t)W * (c->sh.n + 1) * 4))
+        return set_error(CGGI_E_ALIAS, "gates overlap wires");
+    return check_device(c);
 }
 
 } // namespace cggi
@@ -339,29 +366,14 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
                     const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
                     int32_t W, void *stream)
 {
-    if (!ctx)
-        return set_error(CGGI_E_PARAM, "ctx is NULL");
-    if (form != CGGI_FORM_NTT && form != CGGI_FORM_INT8)
-        return set_error(CGGI_E_PARAM, "unknown form");
-    if (!(ctx->forms & (uint32_t)form))
-        return set_error(CGGI_E_UNSUPPORTED, "form not built into the context");
-    if (G < 0 || G > (1 << 22) || W < 1 || W > (1 << 26))
-        return set_error(CGGI_E_SHAPE, "need 0 <= G <= 2^22, 1 <= W <= 2^26");
-    if (G == 0)
-        return CGGI_OK;
-    if (!d_gates || !d_wires || !aligned4(d_gates) || !aligned4(d_wires))
-        return set_error(CGGI_E_SHAPE, "gates/wires must be non-NULL and "
-                                       "4-byte aligned");
-    if (overlap(d_gates, (size_t)G * sizeof(cggi_gate_t), d_wires,
-                (size_t)W * (ctx->sh.n + 1) * 4))
-        return set_error(CGGI_E_ALIAS, "gates overlap wires");
-    int rc = check_device(ctx);
-    if (rc)
+    int rc = level_args_check(ctx, form, d_gates, G, d_wires, W);
+    if (rc || G == 0)
         return rc;
     hipStream_t s = (hipStream_t)stream;
     if ((rc = reserve(ctx, G, s)))
         return rc;
-    return level_launch(ctx, form, d_gates, G, d_wires, W, s);
+    LevelWs ws{ctx->ws_small, ctx->ws_big, ctx->ws_slot, ctx->ws_count};
+    return level_launch(ctx, form, d_gates, G, d_wires, W, ws, true, s);
 }
 
 int cggi_ctx_profile(cggi_ctx *ctx, int enable)
@@ -500,8 +512,15 @@ int cggi_ctx_latency_abort(cggi_ctx *ctx)
         return rc;
     if (!ctx->x_err)
         return CGGI_OK;
+    // a stream that does not wait for the legacy default stream, so the
+    // write lands while latency-mode kernels on any stream still run
+    if (!ctx->abort_stream)
+        CGGI_HIP_TRY(hipStreamCreateWithFlags(&ctx->abort_stream,
+                                              hipStreamNonBlocking));
     const uint32_t one = 1;
-    CGGI_HIP_TRY(hipMemcpy(ctx->x_err, &one, 4, hipMemcpyHostToDevice));
+    CGGI_HIP_TRY(hipMemcpyAsync(ctx->x_err, &one, 4, hipMemcpyHostToDevice,
+                                ctx->abort_stream));
+    CGGI_HIP_TRY(hipStreamSynchronize(ctx->abort_stream));
     return CGGI_OK;
 }
 

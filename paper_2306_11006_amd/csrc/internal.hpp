@@ -47,6 +47,7 @@ struct cggi_ctx {
     size_t x_words[3] = {0, 0, 0};
     uint32_t *x_epoch[3] = {};    // [groups] launch epochs
     uint32_t *x_err = nullptr;    // [1] set when a member's wait timed out
+    hipStream_t abort_stream = nullptr; // non-blocking, for latency_abort
     // INT8 kernel plan (cggi_ctx_int8_plan): entry k runs the batches of
     // (cap[k-1], cap[k]] bootstraps with kernel kind[k]; plan_n = 0 selects
     // the built-in plan.  kind_limit: most bootstraps one launch of each
@@ -114,7 +115,8 @@ int keyswitch_launch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
                      hipStream_t s);
 
 // Brackets one kernel launch with profiling events when enabled and the
-// stream is not capturing.  kind: 0 = bootstrap, 1 = key switch.
+// stream is not capturing.  kind: 0 = bootstrap, 1 = key switch.  A null
+// context records nothing.
 class ProfScope {
   public:
     ProfScope(Ctx *c, int kind, hipStream_t s);
@@ -126,7 +128,23 @@ class ProfScope {
     long idx_ = -1;
 };
 
+// Device buffers of one level: bootstrap inputs [2G][n+1], bootstrap
+// outputs [2G][N+1], first slot of each gate [G], bootstrap count [1].
+struct LevelWs {
+    uint32_t *small;
+    uint32_t *big;
+    int32_t *slot;
+    int32_t *count;
+};
+
+// Launch one level on `ws`; `prof` brackets its kernels with the
+// context's profiling events (when profiling is enabled).
 int level_launch(Ctx *c, cggi_form_t form, const cggi_gate_t *gates, int G,
-                 uint32_t *wires, int W, hipStream_t s);
+                 uint32_t *wires, int W, const LevelWs &ws, bool prof,
+                 hipStream_t s);
+
+// Host-side checks shared by the level entry points (before any launch).
+int level_args_check(Ctx *c, cggi_form_t form, const cggi_gate_t *gates,
+                     int32_t G, uint32_t *wires, int32_t W);
 
 } // namespace cggi

@@ -153,28 +153,30 @@ __global__ __launch_bounds__(256) void k_level_preop(
 } // namespace
 
 int level_launch(Ctx *c, cggi_form_t form, const cggi_gate_t *gates, int G,
-                 uint32_t *wires, int W, hipStream_t s)
+                 uint32_t *wires, int W, const LevelWs &ws, bool prof,
+                 hipStream_t s)
 {
     const Shape &sh = c->sh;
+    Ctx *pc = prof ? c : nullptr;
     hipLaunchKernelGGL(k_level_slots, dim3(1), dim3(SLOT_THREADS), 0, s,
-                       gates, G, W, c->ws_slot, c->ws_count);
+                       gates, G, W, ws.slot, ws.count);
     CGGI_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_level_preop, dim3(G), dim3(256), 0, s, gates,
-                       c->ws_slot, wires, c->ws_small, W, sh.n);
+                       ws.slot, wires, ws.small, W, sh.n);
     CGGI_HIP_TRY(hipGetLastError());
     int rc;
     {
-        ProfScope ps(c, 0, s);
+        ProfScope ps(pc, 0, s);
         rc = form == CGGI_FORM_INT8
-                 ? int8_bootstrap(c, c->ws_small, nullptr, c->ws_big, 2 * G,
-                                  c->ws_count, s)
-                 : ntt_bootstrap(c, c->ws_small, nullptr, c->ws_big, 2 * G,
-                                 c->ws_count, s);
+                 ? int8_bootstrap(c, ws.small, nullptr, ws.big, 2 * G,
+                                  ws.count, s)
+                 : ntt_bootstrap(c, ws.small, nullptr, ws.big, 2 * G,
+                                 ws.count, s);
     }
     if (rc != CGGI_OK)
         return rc;
-    ProfScope ps(c, 1, s);
-    return keyswitch_level(c, gates, c->ws_slot, c->ws_big, wires, G, W, s);
+    ProfScope ps(pc, 1, s);
+    return keyswitch_level(c, gates, ws.slot, ws.big, wires, G, W, s);
 }
 
 } // namespace cggi

@@ -12,6 +12,12 @@ upload of the input ciphertexts from pinned host memory and the download of
 the output ciphertexts (the transfer-inclusive latency), and a replay of the
 whole circuit captured as one HIP graph.  One JSON line per case.
 
+Every figure is guarded: after each case the context's latency-mode error
+word is checked (a timed-out latency-mode launch exits early and would time
+as almost nothing), and when both forms run, the int8 form's final wires
+must equal the NTT form's on every coefficient.  A failed check exits with
+a non-zero status after printing what failed.
+
 Keys and input ciphertexts are uniform random words of the right shapes
 (seeded): the kernels' work and timing do not depend on whether the words
 form a valid encryption, and no decryption is made here.
@@ -86,7 +92,8 @@ def time_case(ctx, p, form, nl, ins, outs, reps, seed):
     torch.cuda.synchronize()
     replay = timed(graph.replay)
     del graph
-    return circ, eager, moved, replay
+    ctx.check()        # raises CggiError E_TIMEOUT after a latency time-out
+    return circ, eager, moved, replay, wires.cpu()
 
 
 def main(argv=None):
@@ -109,14 +116,27 @@ def main(argv=None):
     bsk, ksk = inputs.uniform_keys(p, a.seed)
     ctx = cggi.Context(p, cggi.to_device(bsk), cggi.to_device(ksk),
                        forms=tuple(a.form))
+    failed = False
     for op in a.op:
         for style in a.style or STYLES[op]:
             if style not in STYLES[op]:
                 continue
             nl, ins, outs = build(op, a.bits, style)
+            final = {}
             for form in a.form:
-                circ, eager, moved, replay = time_case(
-                    ctx, p, form, nl, ins, outs, a.reps, a.seed + 1)
+                try:
+                    circ, eager, moved, replay, final[form] = time_case(
+                        ctx, p, form, nl, ins, outs, a.reps, a.seed + 1)
+                except cggi.CggiError as e:
+                    print(json.dumps({"circuit": f"{op}{a.bits}-{style}",
+                                      "form": form, "error": str(e)}),
+                          flush=True)
+                    failed = True
+                    continue
+                agree = None
+                if len(final) == 2:
+                    agree = bool(torch.equal(final["int8"], final["ntt"]))
+                    failed |= not agree
                 print(json.dumps({
                     "circuit": f"{op}{a.bits}-{style}", "form": form,
                     "params": p.name, "gates": int(len(circ.gates)),
@@ -130,9 +150,13 @@ def main(argv=None):
                     "graph_replay_ms": round(statistics.median(replay), 2),
                     "ms_per_level": round(statistics.median(eager) /
                                           circ.n_levels, 3),
-                    "reps": a.reps, "data": "uniform random keys and "
+                    "reps": a.reps, "checked": "ctx.check ok",
+                    "forms_agree": agree,
+                    "data": "uniform random keys and "
                     "ciphertexts (seeded)"}), flush=True)
     ctx.close()
+    if failed:
+        raise SystemExit("latency: a check failed (see the lines above)")
 
 
 if __name__ == "__main__":

@@ -49,22 +49,40 @@ def widths_grid(limits, cus, gpt, max_width=4096):
     return sorted(pts)
 
 
-def plan_from_winners(winners):
+MAX_ENTRIES = 8          # cggi_ctx_int8_plan takes at most eight entries
+
+
+def plan_from_winners(winners, max_entries=MAX_ENTRIES):
     """[(width, kind)] sorted by width -> plan [(kind, cap)]: runs of one
     kind merge into one entry capped at the run's last width; the last entry
-    holds every larger batch."""
-    plan = []
+    holds every larger batch.  While there are more than `max_entries`
+    entries, the run with the fewest winning widths (the first such, never
+    the catch-all last entry) is merged into the run after it, which then
+    also takes the smaller widths; that keeps every latency-mode cap within
+    its kind's limit, since a run's cap never grows."""
+    runs = []                                   # [kind, [widths]]
     for w, k in winners:
-        if plan and plan[-1][0] == k:
-            plan[-1] = (k, w)
+        if runs and runs[-1][0] == k:
+            runs[-1][1].append(w)
         else:
-            plan.append((k, w))
-    if not plan:
+            runs.append([k, [w]])
+    if not runs:
         return [("tiles4", MAX_CAP)]
-    if plan[-1][0].startswith("split"):
-        plan.append(("tiles4", MAX_CAP))
-    else:
-        plan[-1] = (plan[-1][0], MAX_CAP)
+    if runs[-1][0].startswith("split"):
+        runs.append(["tiles4", []])
+    while len(runs) > max_entries:
+        i = min(range(len(runs) - 1), key=lambda j: len(runs[j][1]))
+        runs[i + 1][1][:0] = runs[i][1]
+        del runs[i]
+        merged = []
+        for k, ws in runs:
+            if merged and merged[-1][0] == k:
+                merged[-1][1].extend(ws)
+            else:
+                merged.append([k, ws])
+        runs = merged
+    plan = [(k, ws[-1]) for k, ws in runs[:-1]]
+    plan.append((runs[-1][0], MAX_CAP))
     return plan
 
 
@@ -105,6 +123,10 @@ def _force(ctx, kind, limits):
 
 
 def _time(ctx, form, x, out, reps):
+    """Mean kernel ms of `reps` bootstraps of x into out.  The context's
+    latency-mode error word is checked afterwards: a timed-out latency-mode
+    launch exits early and would otherwise time as almost nothing (raises
+    CggiError E_TIMEOUT)."""
     ctx.bootstrap(form, x, out)          # warm-up
     torch.cuda.synchronize()
     ctx.profile(True)
@@ -112,6 +134,7 @@ def _time(ctx, form, x, out, reps):
         ctx.bootstrap(form, x, out)
     ms, n, _, _ = ctx.profile_read()
     ctx.profile(False)
+    ctx.check()
     return ms / max(n, 1)
 
 
@@ -119,7 +142,9 @@ def autotune(ctx, p, widths=None, reps=3, time_ntt=True, seed=1,
              max_width=4096):
     """Time every int8 kernel (and the NTT form) per width; return the table
     {"plan": [(kind, cap)], "times": {w: {kind: ms}}, "forms": {w: {form:
-    ms}}, ...}.  The context's plan is restored to the built-in one."""
+    ms}}, ...}.  Every timed kernel's outputs must equal those of the first
+    one timed at that width (the NTT form when the context has it), else
+    RuntimeError.  The context's plan is restored to the built-in one."""
     limits = ctx.int8_limits()
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     gpt = 1024 // p.N if p.N <= 1024 else 1
@@ -134,24 +159,32 @@ def autotune(ctx, p, widths=None, reps=3, time_ntt=True, seed=1,
     try:
         for w in widths:
             x = cts[:w]
+            ref = None
+            f = {}
+            if has_ntt:
+                f["ntt"] = round(_time(ctx, "ntt", x, out[:w], reps), 4)
+                ref = out[:w].clone()
             row = {}
             for kind in cggi.KINDS:
                 if limits[kind] < w:
                     continue
                 _force(ctx, kind, limits)
                 row[kind] = round(_time(ctx, "int8", x, out[:w], reps), 4)
+                if ref is None:
+                    ref = out[:w].clone()
+                elif not torch.equal(out[:w], ref):
+                    raise RuntimeError(f"tune: kernel {kind} at width {w} "
+                                       "disagrees with the reference outputs")
             best = min(row, key=row.get)
             winners.append((w, best))
             times[str(w)] = row
-            f = {"int8": row[best]}
-            if has_ntt:
-                f["ntt"] = round(_time(ctx, "ntt", x, out[:w], reps), 4)
+            f["int8"] = row[best]
             forms[str(w)] = f
     finally:
         ctx.int8_plan(None)
     return {"params": p.name, "device": torch.cuda.get_device_name(0),
             "cus": cus, "limits": limits, "widths": widths, "reps": reps,
-            "times": times, "forms": forms,
+            "times": times, "forms": forms, "checked": True,
             "plan": plan_from_winners(winners)}
 
 
@@ -170,9 +203,10 @@ def load_or_tune(ctx, p, path=None, **kw):
     if os.path.exists(path):
         with open(path) as f:
             table = json.load(f)
-        if table.get("key") == key:
+        if table.get("key") == key and table.get("checked"):
             return table
     table = autotune(ctx, p, **kw)
+    ctx.check()            # no latency-mode time-out since the timings
     table["key"] = key
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
     tmp = path + ".tmp"

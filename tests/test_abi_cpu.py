@@ -91,10 +91,10 @@ def test_create_rejects_bad_arguments_before_any_gpu_work():
                              ctypes.byref(h)) == cggi.E_PARAM
     assert b"bg_bit" in L.cggi_last_error()
     assert h.value is None
-    # int8 form at N=1024 with eight digit rows (Bg=2^13, l=2): the
+    # int8 form at N=1024 with sixteen digit rows (Bg=2^3, l=8): the
     # workgroup's digit operands no longer fit the 160 KB of LDS
-    pw = cggi.params_struct(dataclasses.replace(params.DEFAULT, bg_bit=13,
-                                                l=2))
+    pw = cggi.params_struct(dataclasses.replace(params.DEFAULT, bg_bit=3,
+                                                l=8))
     assert L.cggi_params_check(ctypes.byref(pw)) == cggi.OK
     assert L.cggi_ctx_create(ctypes.byref(pw), ctypes.c_void_p(16),
                              ctypes.c_void_p(16), 2, None,
@@ -127,3 +127,86 @@ def test_batch_calls_reject_null_context():
     assert L.cggi_ctx_int8_limits(None, None) == cggi.E_PARAM
     assert L.cggi_ctx_latency_abort(None) == cggi.E_PARAM
     assert L.cggi_ctx_destroy(None) == cggi.OK
+
+
+def test_int8_form_rejects_more_than_eight_gadget_levels():
+    """The INT8 form's generic digit loops cover at most 8 gadget levels;
+    a context with more is refused on the host (N=2048, l=9, Bg=2^3 would
+    otherwise fit the LDS)."""
+    import ctypes
+    import dataclasses
+    L = cggi.lib()
+    h = ctypes.c_void_p()
+    p9 = dataclasses.replace(params.LARGE, bg_bit=3, l=9)
+    ps = cggi.params_struct(p9)
+    assert L.cggi_params_check(ctypes.byref(ps)) == cggi.OK
+    assert L.cggi_ctx_create(ctypes.byref(ps), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), 2, None,
+                             ctypes.byref(h)) == cggi.E_PARAM
+    assert b"l must be <= 8" in L.cggi_last_error()
+    assert h.value is None
+    # l = 8 passes the host checks of the INT8 form (it fails later only
+    # for want of a GPU, past every parameter check)
+    p8 = cggi.params_struct(dataclasses.replace(params.LARGE, bg_bit=3, l=8))
+    rc = L.cggi_ctx_create(ctypes.byref(p8), ctypes.c_void_p(16),
+                           ctypes.c_void_p(16), 2, None, ctypes.byref(h))
+    assert rc != cggi.E_PARAM or b"l must be" not in L.cggi_last_error()
+
+
+def _fake_context(p):
+    """A Context object that never reached the C ABI (no GPU needed): the
+    wrapper's own argument checks run before any pointer is passed."""
+    ctx = cggi.Context.__new__(cggi.Context)
+    ctx.params = p
+    ctx.forms = ("ntt", "int8")
+    ctx._h = None
+    return ctx
+
+
+def test_wrapper_rejects_bad_shapes_before_the_c_call():
+    import torch
+    p = params.TOY
+    ctx = _fake_context(p)
+    n1, N1 = p.n + 1, p.N + 1
+    i32 = torch.int32
+    bad = [
+        lambda: ctx.bootstrap("int8", torch.zeros(n1, dtype=i32)),  # 1-D
+        lambda: ctx.bootstrap("int8", torch.zeros((4, N1), dtype=i32)),
+        lambda: ctx.bootstrap("int8", torch.zeros((4, n1), dtype=i32),
+                              out=torch.zeros((3, N1), dtype=i32)),
+        lambda: ctx.bootstrap("int8", torch.zeros((4, n1), dtype=i32),
+                              out=torch.zeros((4, N1), dtype=i32),
+                              testv=torch.zeros(p.N - 1, dtype=i32)),
+        lambda: ctx.keyswitch(torch.zeros((4, n1), dtype=i32)),
+        lambda: ctx.keyswitch(torch.zeros((4, N1), dtype=i32),
+                              out=torch.zeros((4, N1), dtype=i32)),
+        lambda: ctx.eval_level("int8", torch.zeros((3, 4), dtype=i32),
+                               torch.zeros((8, n1), dtype=i32)),
+        lambda: ctx.eval_level("int8", torch.zeros(15, dtype=i32),
+                               torch.zeros((8, n1), dtype=i32)),
+        lambda: ctx.eval_level("int8", torch.zeros((3, 5), dtype=i32),
+                               torch.zeros((8, n1 - 1), dtype=i32)),
+    ]
+    for k, f in enumerate(bad):
+        with pytest.raises(ValueError):
+            f()
+            raise AssertionError(f"case {k} passed")
+
+
+def test_context_rejects_wrong_key_sizes_before_the_c_call():
+    import torch
+    p = params.TOY
+    bsk = torch.zeros(p.bsk_shape, dtype=torch.int32)
+    ksk = torch.zeros(p.ksk_shape, dtype=torch.int32)
+    with pytest.raises(ValueError, match="bsk"):
+        cggi.Context(p, bsk[:-1], ksk)
+    with pytest.raises(ValueError, match="ksk"):
+        cggi.Context(p, bsk, ksk[:, :-1])
+
+
+def test_mulmod_ceiling_rejects_bad_arguments():
+    import ctypes
+    L = cggi.lib()
+    out = ctypes.c_double()
+    assert L.cggi_measure_mulmod(0, ctypes.byref(out)) == cggi.E_PARAM
+    assert L.cggi_measure_mulmod(10, None) == cggi.E_PARAM

@@ -88,3 +88,32 @@ def test_dag_cli_needs_gpu():
     from paper_2306_11006_amd import dag
     with pytest.raises(SystemExit, match="no GPU"):
         dag.main(["--gates", "10"])
+
+
+def test_plan_from_winners_keeps_at_most_eight_entries():
+    # noisy alternation between two kernels of similar speed
+    kinds = ("split8", "split4", "split2", "tiles1", "tiles2", "tiles4")
+    win, w = [], 1
+    for k in range(40):
+        win.append((w, kinds[k % 6]))
+        w += 1 + k
+    # every winner respects its kind's limit, as the tuner's would
+    win = [(w, k if LIMITS[k] >= w else "tiles2") for w, k in win]
+    plan = tune.plan_from_winners(win)
+    assert len(plan) <= 8, plan
+    valid(plan)
+    # a strict alternation of two throughput kernels
+    alt = [(w, "tiles1" if i % 2 else "tiles2")
+           for i, w in enumerate(range(200, 230))]
+    plan = tune.plan_from_winners(alt)
+    assert len(plan) <= 8
+    valid(plan)
+    # every width still goes to a kernel whose limit holds it
+    for w, _ in win:
+        k = next(k for k, c in plan if w <= c)
+        assert LIMITS[k] >= w
+    # short plans are untouched
+    short = [(1, "split8"), (16, "split8"), (17, "split4"), (64, "split4"),
+             (65, "tiles4")]
+    assert tune.plan_from_winners(short) == [
+        ("split8", 16), ("split4", 64), ("tiles4", 2**31 - 1)]
