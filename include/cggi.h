@@ -9,7 +9,7 @@
  * steps (rotate, subtract, gadget-decompose, multiply by a TRGSW row of the
  * bootstrapping key, add), sample extraction, and a key switch back to the
  * LWE key.  Section 4.2 ("waves") levelises a gate DAG so that every gate of
- * a level is independent; Section 5.4 runs one batched launch per set of
+ * a level is independent; Section 5.3 runs one batched launch per set of
  * gates.
  *
  * Torus values are uint32_t (Z/2^32; the value u stands for u / 2^32) and
@@ -34,6 +34,7 @@
 #ifndef CGGI_H
 #define CGGI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -50,7 +51,7 @@ typedef struct {
 /* Forms of the negacyclic products inside the blind rotation.  Both give
  * bit-identical results.
  *  NTT : exact NTT modulo Q = 2^64 - 2^32 + 1 with the paper's generator
- *        (Section 5.5), centred lift, low 32 bits.
+ *        (Section 5.4), centred lift, low 32 bits.
  *  INT8: exact split-limb block-Toeplitz GEMM on int8 MFMA with int32
  *        accumulation; each key coefficient is split into four signed
  *        8-bit limbs and the limbs are recombined mod 2^32. */
@@ -101,7 +102,8 @@ int cggi_params_check(const cggi_params_t *params);
  * ([N][t][2^gamma][n+1]) must stay valid and unchanged for the context's
  * life (larger bases gather its rows directly).
  * `stream` is a hipStream_t (NULL = default stream).  On success *out
- * receives the context. */
+ * receives the context.  The INT8 form takes Bg <= 2^13 and l <= 8 (and a
+ * workgroup that fits the LDS); otherwise CGGI_E_PARAM. */
 int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
                     const uint32_t *d_ksk, uint32_t forms, void *stream,
                     cggi_ctx **out);
@@ -201,6 +203,20 @@ int cggi_ctx_profile_read(cggi_ctx *ctx, double *bs_ms, int32_t *bs_launches,
 int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
                            double *tops);
 
+/* Diagnostic: the Goldilocks multiply-mod rate this GPU sustains.  Times a
+ * bare loop of the NTT form's own multiply-mod modulo Q = 2^64 - 2^32 + 1
+ * (Section 5.4's modulus: a 64 x 64 -> 128-bit product from four 32 x 32 +
+ * 64 multiply-adds, then the reduction) on 8 independent chains per
+ * thread, two workgroups of 512 threads per CU (the NTT form's launch
+ * shape), `iters` iterations, random residues; writes tera multiply-mods
+ * per second to *tmulmods.  An upper bound for the NTT form, whose
+ * butterflies also add, subtract and address.  Not a batch call: it
+ * allocates and frees 32 KB plus one word per thread of device memory,
+ * runs on the default stream of the current device and waits for
+ * completion.  CGGI_E_PARAM for iters < 1 or tmulmods NULL, CGGI_E_HIP on
+ * a runtime error. */
+int cggi_measure_mulmod(int32_t iters, double *tmulmods);
+
 /* Latency mode of the INT8 form (N <= 1024).  ArctyrEX's closing section
  * names splitting one gate over several SMs as the way to speed up narrow
  * circuit levels; here a narrow batch runs each column tile's blind
@@ -232,7 +248,9 @@ int cggi_ctx_latency_mode(cggi_ctx *ctx, int32_t enable);
 int cggi_ctx_latency_groups(const cggi_ctx *ctx, int32_t *groups);
 int cggi_ctx_check(cggi_ctx *ctx);
 /* Sets the context's latency-mode error word from the host at once (not
- * stream-ordered), as a time-out would: latency-mode kernels still running
+ * stream-ordered: the write goes through a non-blocking stream of the
+ * context, so it does not queue behind kernels on the default stream or
+ * any other), as a time-out would: latency-mode kernels still running
  * stop at their next poll, later ones do nothing (their outputs are left
  * untouched) until cggi_ctx_check, which then returns CGGI_E_TIMEOUT and
  * clears the state.  Other INT8 kernels and the NTT form are unaffected.

@@ -1,4 +1,4 @@
-// diag.hip -- a measured ceiling for the int8 MFMA roofline.
+// diag.hip -- measured ceilings for the rooflines of the two forms.
 //
 // The int8 blind rotation is bound by v_mfma_i32_32x32x32_i8.  The published
 // dense int8 rate assumes the top engine clock; with random operands the GPU
@@ -6,6 +6,15 @@
 // bare loop of that MFMA on the same launch shape the int8 form uses (one
 // workgroup of 8 waves per CU, 8 independent accumulators per wave) and
 // reports the rate, with random or all-zero operands.
+//
+// The NTT form is bound by integer VALU work, most of it the Goldilocks
+// multiply-mod (a 64 x 64 -> 128-bit product from four 32 x 32 + 64
+// multiply-adds and the reduction modulo Q).  A second routine times a bare
+// loop of that same multiply-mod (gl::mul, the routine the NTT kernel
+// calls) on independent chains, on the NTT form's launch shape (two
+// workgroups of 512 threads per CU), which bounds the multiply-mods per
+// second the NTT form could reach if it did nothing else.
+#include "goldilocks.hpp"
 #include "internal.hpp"
 
 #include <vector>
@@ -43,8 +52,101 @@ __global__ __launch_bounds__(DIAG_THREADS, 1) void k_mfma_loop(
     out[blockIdx.x * DIAG_THREADS + threadIdx.x] = s;
 }
 
+constexpr int MM_THREADS = 512;
+constexpr int MM_CHAINS = 8;             // independent chains per thread
+
+__global__ __launch_bounds__(MM_THREADS) void k_mulmod_loop(
+    const uint64_t *__restrict__ seeds, int iters, uint64_t *__restrict__ out)
+{
+    const int t = threadIdx.x;
+    uint64_t x[MM_CHAINS], y[MM_CHAINS];
+#pragma unroll
+    for (int j = 0; j < MM_CHAINS; ++j) {
+        x[j] = seeds[(t * MM_CHAINS + j) & (DIAG_TABLE - 1)] % gl::Q;
+        y[j] = seeds[(t * MM_CHAINS + j + 7) & (DIAG_TABLE - 1)] % gl::Q;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int j = 0; j < MM_CHAINS; ++j)
+            x[j] = gl::mul(x[j], y[j]);
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < MM_CHAINS; ++j)
+        s ^= x[j];
+    out[(size_t)blockIdx.x * MM_THREADS + t] = s;
+}
+
 } // namespace
 } // namespace cggi
+
+extern "C" int cggi_measure_mulmod(int32_t iters, double *tmulmods)
+{
+    using namespace cggi;
+    if (iters < 1 || !tmulmods)
+        return set_error(CGGI_E_PARAM,
+                         "iters must be >= 1 and tmulmods non-NULL");
+    int dev = 0, cus = 0;
+    CGGI_HIP_TRY(hipGetDevice(&dev));
+    CGGI_HIP_TRY(hipDeviceGetAttribute(
+        &cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int blocks = 2 * cus;
+    std::vector<uint64_t> h(DIAG_TABLE);
+    uint64_t x = 0x2306ull;
+    for (auto &v : h) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull; // MMIX LCG
+        v = x;
+    }
+    void *seeds = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = CGGI_OK;
+    float ms = 0.f;
+    auto fail = [&](hipError_t e) {
+        if (rc == CGGI_OK && e != hipSuccess)
+            rc = set_error(CGGI_E_HIP, hipGetErrorString(e));
+    };
+    fail(hipMalloc(&seeds, h.size() * sizeof(uint64_t)));
+    if (rc == CGGI_OK)
+        fail(hipMalloc(&out, (size_t)blocks * MM_THREADS * sizeof(uint64_t)));
+    if (rc == CGGI_OK)
+        fail(hipMemcpy(seeds, h.data(), h.size() * sizeof(uint64_t),
+                       hipMemcpyHostToDevice));
+    if (rc == CGGI_OK)
+        fail(hipEventCreate(&e0));
+    if (rc == CGGI_OK)
+        fail(hipEventCreate(&e1));
+    if (rc == CGGI_OK) {
+        hipLaunchKernelGGL(k_mulmod_loop, dim3(blocks), dim3(MM_THREADS), 0,
+                           0, static_cast<const uint64_t *>(seeds), 64,
+                           static_cast<uint64_t *>(out));
+        fail(hipGetLastError());
+    }
+    if (rc == CGGI_OK)
+        fail(hipEventRecord(e0, 0));
+    if (rc == CGGI_OK) {
+        hipLaunchKernelGGL(k_mulmod_loop, dim3(blocks), dim3(MM_THREADS), 0,
+                           0, static_cast<const uint64_t *>(seeds), iters,
+                           static_cast<uint64_t *>(out));
+        fail(hipGetLastError());
+    }
+    if (rc == CGGI_OK)
+        fail(hipEventRecord(e1, 0));
+    if (rc == CGGI_OK)
+        fail(hipEventSynchronize(e1));
+    if (rc == CGGI_OK)
+        fail(hipEventElapsedTime(&ms, e0, e1));
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipFree(seeds);
+    (void)hipFree(out);
+    if (rc != CGGI_OK)
+        return rc;
+    const double total = (double)blocks * MM_THREADS * MM_CHAINS * iters;
+    *tmulmods = total / (ms * 1e-3) / 1e12;
+    return CGGI_OK;
+}
 
 extern "C" int cggi_measure_int8_mfma(int32_t iters, int32_t random_operands,
                                       double *tops)
