@@ -239,3 +239,64 @@ def test_alias_rejected(default_uniform):
     with pytest.raises(cggi.CggiError) as e:
         ctx.keyswitch(buf, buf)
     assert e.value.code == cggi.E_ALIAS
+
+
+def crafted_modswitch_inputs(p, seed):
+    """Eight LWE ciphertexts whose coefficients sit on and next to the
+    modulus switch's rounding ties (u = k 2^(32-s) + 2^(31-s), 2N = 2^s,
+    rounded up) and on the values that switch to 0 (so the CMux steps with
+    a~_i = 0 are skipped): exact ties, ties - 1, ties + 1, all-zero masks,
+    masks 90% of which round to 0, masks at the wrap 2^32 - 2^(31-s) (-> 0)
+    and one below it (-> 2N - 1), the pair 2^(31-s) - 1 / 2^(31-s) (-> 0 / 1),
+    and one uniform row."""
+    log2_2n = (2 * p.N).bit_length() - 1
+    drop = 32 - log2_2n
+    half = 1 << (drop - 1)
+    g = inputs.rng(seed)
+    m = p.n + 1
+    k = g.integers(0, 2 * p.N, size=(8, m), dtype=np.int64)
+    tie = (k << drop) + half
+    rows = np.empty((8, m), dtype=np.int64)
+    rows[0] = tie[0]
+    rows[1] = tie[1] - 1
+    rows[2] = tie[2] + 1
+    rows[3] = 0
+    rows[3, -1] = tie[3, -1]
+    small = g.integers(-half, half, size=m)
+    rows[4] = np.where(g.random(m) < 0.9, small, tie[4])
+    wrap = (1 << 32) - half
+    rows[5] = np.where(np.arange(m) % 2 == 0, wrap, wrap - 1)
+    rows[6] = np.where(np.arange(m) % 2 == 0, half - 1, half)
+    rows[6, -1] = (1 << 32) - 1
+    rows[7] = g.integers(0, 1 << 32, size=m)
+    return (rows % (1 << 32)).astype(np.uint32)
+
+
+@pytest.mark.parametrize("pname", ["toy", "default"])
+def test_modswitch_ties_and_zero_rotations(O, torch_cuda, pname):
+    """Crafted inputs on the modulus switch's ties and on rotations that
+    switch to 0: the NTT form and every int8 kernel kind (forced through the
+    kernel plan) equal the oracle on every output coefficient."""
+    from paper_2306_11006_amd import cggi
+    p = params.ALL[pname]
+    bsk, ksk = inputs.uniform_keys(p, 6100)
+    ctx = make_ctx(p, bsk, ksk)
+    cts = crafted_modswitch_inputs(p, 6101)
+    want = np.stack(oracle_map(lambda x: O.bootstrap(p, bsk, x), cts))
+    say(f"{pname} modswitch ties form=ntt")
+    assert np.array_equal(gpu_bootstrap(ctx, "ntt", cts), want)
+    limits = ctx.int8_limits()
+    for kind in cggi.KINDS:
+        if limits[kind] < len(cts):
+            continue
+        if kind.startswith("split"):
+            ctx.int8_plan([(kind, limits[kind]), ("tiles4", cggi.INT32_MAX)])
+        else:
+            ctx.int8_plan([(kind, cggi.INT32_MAX)])
+        say(f"{pname} modswitch ties form=int8 kind={kind}")
+        got = gpu_bootstrap(ctx, "int8", cts)
+        ctx.check()
+        bad = np.nonzero((got != want).any(axis=1))[0].tolist()
+        assert not bad, (kind, bad)
+    ctx.int8_plan(None)
+    ctx.close()
