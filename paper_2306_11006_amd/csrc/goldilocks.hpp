@@ -1,6 +1,6 @@
 // goldilocks.hpp -- arithmetic modulo Q = 2^64 - 2^32 + 1 on gfx950.
 //
-// The modulus of the paper's exact NTT (Section 5.5): 2^64 = 2^32 - 1 and
+// The modulus of the paper's exact NTT (Section 5.4): 2^64 = 2^32 - 1 and
 // 2^96 = -1 (mod Q), so a 128-bit product reduces with a few 64-bit adds.
 // All functions take and return canonical residues in [0, Q).
 #pragma once

@@ -4,7 +4,7 @@
 // transforms of the decomposed digit polynomials, pointwise product with
 // the transformed TRGSW row, inverse transforms, add into the accumulator)
 // is computed exactly modulo Q = 2^64 - 2^32 + 1 with psi = g^(2^32 / 2N)
-// for the paper's generator g (Section 5.5).  Since every exact sum is
+// for the paper's generator g (Section 5.4).  Since every exact sum is
 // below Q/2 in magnitude (checked on the host), the centred lift of the
 // result equals the integer product, and its low 32 bits are the product
 // mod 2^32.

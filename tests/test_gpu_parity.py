@@ -236,8 +236,9 @@ def test_alias_rejected(default_uniform):
         with pytest.raises(cggi.CggiError) as e:
             ctx.bootstrap(form, view, buf)
         assert e.value.code == cggi.E_ALIAS
+    # a correctly shaped output that overlaps the input reaches the library
     with pytest.raises(cggi.CggiError) as e:
-        ctx.keyswitch(buf, buf)
+        ctx.keyswitch(buf, view)
     assert e.value.code == cggi.E_ALIAS
 
 
