@@ -159,6 +159,26 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
                     const cggi_gate_t *d_gates, int32_t G, uint32_t *d_wires,
                     int32_t W, void *stream);
 
+/* cggi_eval_level for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same level, the same kernels and bit-identical wires,
+ * but the level's workspace (bootstrap slots, bootstrap inputs [2G][n+1]
+ * and outputs [2G][N+1]) lives in a fixed 64 MiB device array of the
+ * library instead of the context's reserved workspace, so no
+ * cggi_ctx_reserve is needed and nothing is allocated or freed: no
+ * hipMalloc, hipFree or allocating library call, and no profiling events.
+ * Every GPU the library runs on holds its own copy of that array from the
+ * first context created on it until the process ends.  Limit: G may be at
+ * most floor(~64 MiB / (4 + 8(n+1) + 8(N+1))) gates (5,063 at n=630,
+ * N=1024; 3,003 at n=742, N=2048); a larger G returns CGGI_E_SHAPE with
+ * the limit in the message and launches nothing.  All calls on one GPU
+ * share the one array: calls that may overlap on a GPU (several streams,
+ * several contexts, several host threads) race and must be serialised by
+ * the caller.  Arguments, contract and other errors as cggi_eval_level. */
+int cggi_eval_level_noalloc(cggi_ctx *ctx, cggi_form_t form,
+                            const cggi_gate_t *d_gates, int32_t G,
+                            uint32_t *d_wires, int32_t W, void *stream);
+
 /* Levelise a gate DAG on the host (Section 4.2, "waves"): every gate gets
  * level 1 + max(level of the gates producing its inputs), 0 when all its
  * inputs are circuit inputs (wires no gate writes); gates are visited in

@@ -32,7 +32,7 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_ctx_latency_mode", "cggi_ctx_latency_groups",
            "cggi_ctx_check", "cggi_ctx_int8_plan", "cggi_ctx_int8_plan_get",
            "cggi_ctx_int8_limits", "cggi_ctx_latency_abort",
-           "cggi_last_error"]
+           "cggi_eval_level_noalloc", "cggi_last_error"]
 
 # INT8 kernel kinds of a plan (cggi_ctx_int8_plan), in the header's order
 KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4", "split8")
@@ -73,6 +73,8 @@ def lib():
                                            vp]
         L.cggi_keyswitch_batch.argtypes = [vp, vp, vp, i32, vp]
         L.cggi_eval_level.argtypes = [vp, ctypes.c_int, vp, i32, vp, i32, vp]
+        L.cggi_eval_level_noalloc.argtypes = [vp, ctypes.c_int, vp, i32, vp,
+                                              i32, vp]
         L.cggi_levelize.argtypes = [vp, i32, i32, vp, vp,
                                     ctypes.POINTER(i32), vp]
         L.cggi_ctx_profile.argtypes = [vp, ctypes.c_int]
@@ -330,6 +332,19 @@ class Context:
         W = wires.shape[0]
         _check(lib().cggi_eval_level(self._h, _form(form), _ptr(gates), G,
                                      _ptr(wires), W, _stream(stream)))
+        return wires
+
+    def eval_level_noalloc(self, form, gates, wires, stream=None):
+        """eval_level on the library's fixed device workspace
+        (cggi_eval_level_noalloc): allocates nothing, no reserve needed;
+        calls that overlap on one GPU race."""
+        _shape(gates, "gates", None, 5)
+        _shape(wires, "wires", None, self.params.n + 1)
+        G = gates.shape[0]
+        W = wires.shape[0]
+        _check(lib().cggi_eval_level_noalloc(self._h, _form(form),
+                                             _ptr(gates), G, _ptr(wires), W,
+                                             _stream(stream)))
         return wires
 
 

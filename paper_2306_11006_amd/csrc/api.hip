@@ -6,6 +6,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 namespace cggi {
@@ -190,6 +191,74 @@ ProfScope::~ProfScope()
         (void)hipEventRecord(c_->ev_pool[idx_ + 1], s_);
 }
 
+// ---- fixed level workspace of cggi_eval_level_noalloc ---------------------
+// A file-scope device array: every GPU the library runs on holds its own
+// copy, at its own address, from the code object's load until the process
+// ends.  On the host the name `scratch` is only a stand-in symbol, never a
+// device address: host code uses the address hipGetSymbolAddress returns
+// for the current device, taken once per device (at the first context
+// created there) and kept in g_scratch_addr.
+constexpr size_t SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_addr[SCRATCH_MAX_DEVICES];
+
+// This device's address of `scratch` (the device must be current).
+static int scratch_address(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+        return set_error(CGGI_E_PARAM, "device index beyond the scratch "
+                                       "table (64 devices)");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return set_error(CGGI_E_HIP, "hipGetSymbolAddress(scratch) gave "
+                                         "a null address");
+        g_scratch_addr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_addr[dev];
+    return CGGI_OK;
+}
+
+static size_t align256(size_t x)
+{
+    return (x + 255) & ~size_t(255);
+}
+
+// Carve a level's workspace out of `base` (count, slots, bootstrap inputs,
+// bootstrap outputs, each 256-byte aligned); returns the bytes it needs.
+static size_t scratch_layout(const Shape &sh, int64_t G, unsigned char *base,
+                             LevelWs *ws)
+{
+    const size_t slot_off = 256;
+    const size_t small_off = align256(slot_off + (size_t)G * 4);
+    const size_t big_off = align256(small_off + 2 * (size_t)G * (sh.n + 1) * 4);
+    const size_t total = big_off + 2 * (size_t)G * (sh.N + 1) * 4;
+    if (ws && base) {
+        ws->count = reinterpret_cast<int32_t *>(base);
+        ws->slot = reinterpret_cast<int32_t *>(base + slot_off);
+        ws->small = reinterpret_cast<uint32_t *>(base + small_off);
+        ws->big = reinterpret_cast<uint32_t *>(base + big_off);
+    }
+    return total;
+}
+
+// Most gates of one level that fit the fixed workspace.
+static int64_t scratch_max_gates(const Shape &sh)
+{
+    const size_t per = 4 + 2 * (size_t)(sh.n + 1) * 4 + 2 * (size_t)(sh.N + 1) * 4;
+    int64_t g = (int64_t)(SCRATCH_BYTES / per);
+    while (g > 0 && scratch_layout(sh, g, nullptr, nullptr) > SCRATCH_BYTES)
+        --g;
+    return g;
+}
+
 static void prof_clear(Ctx *c)
 {
     c->ev_used = 0;
@@ -259,6 +328,10 @@ int cggi_ctx_create(const cggi_params_t *params, const uint32_t *d_bsk,
                               c->device) != hipSuccess || c->cus < 1) {
         free_ctx(c);
         return set_error(CGGI_E_HIP, "hipGetDevice / CU count failed");
+    }
+    if ((rc = scratch_address(c->device, &c->scratch))) {
+        free_ctx(c);
+        return rc;
     }
     if (forms & CGGI_FORM_NTT) {
         if ((rc = ntt_make_tables(c, s)) || (rc = ntt_transform_bsk(c, d_bsk, s))) {
@@ -374,6 +447,28 @@ int cggi_eval_level(cggi_ctx *ctx, cggi_form_t form,
         return rc;
     LevelWs ws{ctx->ws_small, ctx->ws_big, ctx->ws_slot, ctx->ws_count};
     return level_launch(ctx, form, d_gates, G, d_wires, W, ws, true, s);
+}
+
+int cggi_eval_level_noalloc(cggi_ctx *ctx, cggi_form_t form,
+                            const cggi_gate_t *d_gates, int32_t G,
+                            uint32_t *d_wires, int32_t W, void *stream)
+{
+    int rc = level_args_check(ctx, form, d_gates, G, d_wires, W);
+    if (rc || G == 0)
+        return rc;
+    if (!ctx->scratch)
+        return set_error(CGGI_E_HIP, "the context has no scratch address");
+    const int64_t gmax = scratch_max_gates(ctx->sh);
+    if (G > gmax)
+        return set_error(CGGI_E_SHAPE,
+                         "level of " + std::to_string(G) + " gates exceeds "
+                         "the fixed 64 MiB workspace (at most " +
+                         std::to_string(gmax) + " gates at these parameters)");
+    LevelWs ws{};
+    scratch_layout(ctx->sh, G, ctx->scratch, &ws);
+    // no profiling events here: their creation would allocate
+    return level_launch(ctx, form, d_gates, G, d_wires, W, ws, false,
+                        (hipStream_t)stream);
 }
 
 int cggi_ctx_profile(cggi_ctx *ctx, int enable)

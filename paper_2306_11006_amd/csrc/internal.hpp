@@ -65,6 +65,9 @@ struct cggi_ctx {
     uint32_t *ws_big = nullptr;   // [2G][N+1] bootstrap outputs
     int32_t *ws_slot = nullptr;   // [G] first slot of each gate (-1: none)
     int32_t *ws_count = nullptr;  // [1] number of bootstrap slots
+    // this device's address of the fixed level workspace of
+    // cggi_eval_level_noalloc (taken at context creation)
+    unsigned char *scratch = nullptr;
     // kernel timing (cggi_ctx_profile)
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
