@@ -62,11 +62,13 @@ def code_sha256(path):
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def stored_traffic(profile="profiles/eval_level_1024_nand_default.md"):
+def stored_traffic(profile="profiles/eval_level_1024_nand_default.md",
+                   kernel=None):
     """HBM bytes per launch of the int8 bootstrap kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter runs (each scaled by the factor the same
     counter showed for a copy of known size), or None when the counters were
-    taken on another version of the kernel source."""
+    taken on another version of the kernel source or (when `kernel` is
+    given) on another kernel."""
     try:
         text = open(os.path.join(ROOT, profile)).read()
     except OSError:
@@ -77,6 +79,8 @@ def stored_traffic(profile="profiles/eval_level_1024_nand_default.md"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
+        if kernel is not None and kv["traffic-kernel"] != kernel:
+            return None
         if code_sha256(os.path.join(ROOT, kv["traffic-source"])) != \
                 kv["traffic-code-sha256"]:
             return None
@@ -88,9 +92,32 @@ def stored_traffic(profile="profiles/eval_level_1024_nand_default.md"):
     return int(round(kib * 1024))
 
 
-def int8_ops_per_bootstrap(p):
+def int8_ops_per_bootstrap(p, kind="tiles4"):
+    """int8 MFMA operations one bootstrap issues: the block-Toeplitz GEMM of
+    every CMux step, 2 * 2N * (2lN * S) * 4 limbs * n; the Karatsuba kernel
+    (kind kara2) computes each length-N negacyclic product as three of
+    length N/2, so it issues 3/4 of that."""
     S = 1 if p.bg_bit <= 7 else 2
-    return 2 * (2 * p.N) * (2 * p.l * p.N * S) * 4 * p.n
+    full = 2 * (2 * p.N) * (2 * p.l * p.N * S) * 4 * p.n
+    return full * 3 // 4 if kind == "kara2" else full
+
+
+def int8_kind_for(plan, bootstraps):
+    """Kernel kind of an int8 plan [(kind, cap)] that takes a batch."""
+    for kind, cap in plan:
+        if bootstraps <= cap:
+            return kind
+    return plan[-1][0]
+
+
+def int8_kernel_name(p, kind):
+    L, S = (p.l, 1) if p.bg_bit <= 7 else (p.l, 2)
+    if (L, S) not in ((3, 1), (2, 2)):
+        L, S = 0, 0
+    if kind == "kara2":
+        return f"k_bootstrap_int8_kara<{p.N}, {L}, {S}>"
+    tiles = {"tiles1": 1, "tiles2": 2, "tiles4": 4}.get(kind, 4)
+    return f"k_bootstrap_int8<{p.N}, {L}, {S}, {tiles}>"
 
 
 def ntt_mulmods_per_bootstrap(p):
@@ -380,21 +407,30 @@ def main():
                               f"{ntt_mulmods_per_bootstrap(p):.4g} "
                               "multiply-mods"}
 
+    plan = ctx.int8_plan_get() if "int8" in res else []
+
     def int8_roof(rr, bootstraps):
-        ach = int8_ops_per_bootstrap(p) * bootstraps / \
-            (rr["bs_kernel_ms"] * 1e-3) / 1e12
-        return {"bound": "mfma", "achieved": round(ach, 1),
-                "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
-                "frac": round(ach / PEAK_INT8_TOPS, 4)}
+        kind = int8_kind_for(plan, bootstraps)
+        ops = int8_ops_per_bootstrap(p, kind)
+        ach = ops * bootstraps / (rr["bs_kernel_ms"] * 1e-3) / 1e12
+        r = {"bound": "mfma", "achieved": round(ach, 1),
+             "peak": PEAK_INT8_TOPS, "unit": "TOP/s",
+             "frac": round(ach / PEAK_INT8_TOPS, 4),
+             "kernel": int8_kernel_name(p, kind),
+             "per_launch": f"{bootstraps} bootstraps x {ops:.4g} int8 ops"}
+        if kind == "kara2":
+            # the same bootstraps priced at the full-length Toeplitz GEMM
+            full = int8_ops_per_bootstrap(p)
+            r["schoolbook_equivalent_tops"] = round(
+                full * bootstraps / (rr["bs_kernel_ms"] * 1e-3) / 1e12, 1)
+        return r
 
     if main_form == "int8":
         roof = int8_roof(r, G)
         roof.update({
-            "traffic": stored_traffic() if G == 1024 else None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 counters)",
-            "kernel": "k_bootstrap_int8<1024, 3, 1, 4>",
-            "per_launch": f"{G} bootstraps x {int8_ops_per_bootstrap(p):.4g}"
-                          " int8 ops"})
+            "traffic": (stored_traffic(kernel=roof["kernel"]) if G == 1024
+                        else None),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 counters)"})
     else:
         roof = ntt_roof(r, G)
         roof["traffic"] = None

@@ -277,12 +277,17 @@ int cggi_ctx_check(cggi_ctx *ctx);
  * CGGI_OK also when the context has no latency mode. */
 int cggi_ctx_latency_abort(cggi_ctx *ctx);
 
-/* INT8 kernel plan (autotuning).  The INT8 form has six kernels for a
+/* INT8 kernel plan (autotuning).  The INT8 form has seven kernels for a
  * batch: CGGI_K_SPLIT8, CGGI_K_SPLIT4 and CGGI_K_SPLIT2 (latency mode,
  * eight, four or two workgroups per column tile; N <= 1024),
  * CGGI_K_TILES1, CGGI_K_TILES2
- * (one workgroup per one or two column tiles; N <= 1024) and CGGI_K_TILES4
- * (four tiles, or one bootstrap per workgroup at N = 2048).  A plan is a
+ * (one workgroup per one or two column tiles; N <= 1024), CGGI_K_TILES4
+ * (four tiles, or one bootstrap per workgroup at N = 2048) and
+ * CGGI_K_KARA2 (one Karatsuba level: each negacyclic product of length N
+ * as three of length N/2 over the even and odd coefficients, 3/4 of the
+ * multiply-adds, two column tiles of N/2-length products per workgroup;
+ * N <= 1024 where its workgroup fits the LDS, which costs the context a
+ * second int8 key form of n*R*2*3*4*(N/2+64) bytes).  A plan is a
  * list of entries (kinds[k], caps[k]) with strictly increasing caps: entry
  * k takes the batches of caps[k-1] + 1 .. caps[k] bootstraps (caps[-1] = 0);
  * the last cap must be at least 2^24 (every batch); a latency-mode entry's
@@ -305,13 +310,14 @@ enum {
     CGGI_K_TILES1 = 2,
     CGGI_K_TILES2 = 3,
     CGGI_K_TILES4 = 4,
-    CGGI_K_SPLIT8 = 5
+    CGGI_K_SPLIT8 = 5,
+    CGGI_K_KARA2 = 6
 };
 int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
                        const int32_t *caps, int32_t count);
 int cggi_ctx_int8_plan_get(const cggi_ctx *ctx, int32_t *kinds,
                            int32_t *caps, int32_t max, int32_t *count);
-int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits /* [6] */);
+int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits /* [7] */);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *cggi_last_error(void);

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcggi.so")
-SOURCES = ["api.hip", "ntt_form.hip", "int8_form.hip", "keyswitch.hip",
-           "level.hip", "levelize.cpp", "diag.hip"]
+SOURCES = ["api.hip", "ntt_form.hip", "int8_form.hip", "int8_kara.hip",
+           "keyswitch.hip", "level.hip", "levelize.cpp", "diag.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("CGGI_OFFLOAD_ARCH", "gfx950")

@@ -35,7 +35,8 @@ EXPORTS = ["cggi_params_check", "cggi_ctx_create", "cggi_ctx_destroy",
            "cggi_eval_level_noalloc", "cggi_last_error"]
 
 # INT8 kernel kinds of a plan (cggi_ctx_int8_plan), in the header's order
-KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4", "split8")
+KINDS = ("split4", "split2", "tiles1", "tiles2", "tiles4", "split8",
+         "kara2")
 INT32_MAX = 2**31 - 1
 
 

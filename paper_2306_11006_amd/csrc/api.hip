@@ -120,6 +120,7 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->tw_inv);
     (void)hipFree(c->bsk_i8);
     (void)hipFree(c->corr_i8);
+    (void)hipFree(c->bsk_k8);
     for (int v = 0; v < 3; ++v) {
         (void)hipFree(c->x_buf[v]);
         (void)hipFree(c->x_epoch[v]);
@@ -542,7 +543,7 @@ int cggi_ctx_int8_plan(cggi_ctx *ctx, const int32_t *kinds,
         return set_error(CGGI_E_PARAM, "count must be in [0, 8] and kinds, "
                                        "caps non-NULL");
     for (int k = 0; k < count; ++k) {
-        if (kinds[k] < 0 || kinds[k] > 5 || ctx->kind_limit[kinds[k]] <= 0)
+        if (kinds[k] < 0 || kinds[k] > 6 || ctx->kind_limit[kinds[k]] <= 0)
             return set_error(CGGI_E_PARAM, "plan entry " + std::to_string(k) +
                                                ": kernel kind unavailable");
         if (caps[k] < 1 || (k > 0 && caps[k] <= caps[k - 1]))
@@ -591,7 +592,7 @@ int cggi_ctx_int8_limits(const cggi_ctx *ctx, int32_t *limits)
 {
     if (!ctx || !limits)
         return set_error(CGGI_E_PARAM, "ctx or limits is NULL");
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 7; ++k)
         limits[k] = ctx->kind_limit[k] > INT32_MAX
                         ? INT32_MAX
                         : (int32_t)ctx->kind_limit[k];

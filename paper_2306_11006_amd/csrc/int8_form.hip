@@ -1202,6 +1202,8 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     int rc = int8_attrs<N>(sh);
     if (rc)
         return rc;
+    if ((rc = kara_make_key(c, bsk, s)))
+        return rc;
     rc = split_setup<N>(c, s);
     if (rc)
         return rc;
@@ -1213,6 +1215,7 @@ static int make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     c->kind_limit[3] = N <= 1024 ? ANY : 0;
     c->kind_limit[4] = ANY;
     c->kind_limit[5] = (int64_t)c->split_groups[2] * gpt;
+    c->kind_limit[6] = c->bsk_k8 ? ANY : 0;
     return CGGI_OK;
 }
 
@@ -1252,7 +1255,9 @@ int int8_active_plan(const Ctx *c, int32_t *kind, int32_t *cap)
             k0[n0] = 3;
             c0[n0++] = (int32_t)(2 * c->cus * gpt);
         }
-        k0[n0] = 4;
+        // the widest batches: the Karatsuba kernel where it is available
+        // (3/4 of the MFMA work; 9% faster at 1024 default bootstraps)
+        k0[n0] = c->kind_limit[6] > 0 ? 6 : 4;
         c0[n0++] = INT32_MAX;
     }
     int n = 0;
@@ -1358,6 +1363,9 @@ static int launch_bs_int8_w(const Ctx *c, const uint32_t *in,
             case 3:
                 rc = launch_bs_int8_t<N, L, S, 2>(c, in, testv, out, Bk,
                                                   d_count, a, b, s);
+                break;
+            case 6:
+                rc = kara_launch(c, in, testv, out, Bk, d_count, a, b, s);
                 break;
             default:
                 rc = launch_bs_int8_t<N, L, S, 4>(c, in, testv, out, Bk,

@@ -1,0 +1,556 @@
+// int8_kara.hip -- the int8-MFMA blind rotation with one Karatsuba level.
+//
+// A CMux step (ArctyrEX Fig. 1 loop body) adds sum_r D_r * a_{r,c'} to
+// each accumulator component c' in Z_{2^32}[X]/(X^N+1).  Split every
+// polynomial by coefficient parity, p(X) = p_e(X^2) + X p_o(X^2), and write
+// Z = X^2 (so Z^(N/2) = X^N = -1).  Then
+//   (a d)_even = a_e d_e + Z a_o d_o
+//   (a d)_odd  = a_e d_o + a_o d_e
+//              = a_e d_e + a_o d_o - (a_e - a_o)(d_e - d_o)
+// with every product negacyclic of length H = N/2: three half-length
+// products P1 = a_e d_e, P2 = a_o d_o, P3 = (a_e - a_o)(d_e - d_o) replace
+// one full-length product, 3/4 of the multiply-adds.  The digit
+// differences d_e - d_o of two sub-digits in [-64, 64) lie in [-127, 127],
+// so they and their negations still fit int8; the key differences are
+// formed mod 2^32 before the limb split.  Each half-length product is the
+// block-Toeplitz GEMM of int8_form.hip at length H:
+//   P[32J + rho] = sum_Delta sum_kappa A_Delta[rho][kappa] s(J,Delta)
+//                  D_{(J - Delta) mod H/32}[kappa],
+//   A_Delta[rho][kappa] = a_ext[32 Delta + rho - kappa],
+// on v_mfma_i32_32x32x32_i8 with the key's four int8 limbs recombined mod
+// 2^32.  Everything is exact mod 2^32, so the result is bit-identical to
+// the other forms.
+//
+// Launch layout (N <= 1024): 768 threads = 12 waves (three per SIMD), one
+// workgroup per CU (LDS-limited).  A column tile holds 32/(H/32)
+// bootstraps side by side (two at N = 1024); a workgroup owns two tiles.
+// Wave w computes product P = w >> 2 for output component c' = w & 1 and
+// key limbs 2((w >> 1) & 1), 2((w >> 1) & 1) + 1, both tiles, over all
+// block offsets (2 limbs x 2 tiles = 4 accumulators); the waves of one
+// output component add their recombined sums into the LDS accumulator
+// (mod 2^32, so the order does not matter):
+//   P1 -> even[m] and odd[m];  P2 -> even[m+1] (-even[0] for the top m)
+//   and odd[m];  P3 -> minus odd[m].
+// The accumulator is stored de-interleaved (even and odd halves, each row
+// padded by one dword per 32 so the fold's lanes fall in distinct banks).
+// Digit operands live in LDS in both signs (for the wrapped blocks), key
+// windows (one byte-exact copy per stage, double-buffered, prefetched from
+// global memory a stage ahead) are read as five aligned dwords per lane and
+// byte-aligned in registers.
+#include "internal.hpp"
+
+#include <type_traits>
+
+namespace cggi {
+
+namespace {
+
+typedef int kv4i __attribute__((ext_vector_type(4)));
+typedef int kv16i __attribute__((ext_vector_type(16)));
+
+template <int N> struct KCfg {
+    static constexpr int H = N / 2;          // half length
+    static constexpr int NBH = H / 32;       // blocks per half polynomial
+    static constexpr int BPT = 32 / NBH;     // bootstraps per column tile
+    static constexpr int TILES = 2;          // column tiles per workgroup
+    static constexpr int GPW = TILES * BPT;  // bootstraps per workgroup
+    static constexpr int THREADS = 768;      // 3 products x 2 comps x 2 limb pairs
+    static constexpr int ELEN = H + 64;      // bytes per key window
+    static constexpr int EW = ELEN / 4;      // dwords per key window
+    static constexpr int WIN_DW = 2 * 3 * 4 * EW;  // one stage: c', P, limb
+    static constexpr int AH = H + H / 32;    // padded accumulator half
+    // dwords per bootstrap's accumulators (2 components x 2 halves), = NBH
+    // mod 32 so that the bootstraps of a tile land on distinct banks
+    static constexpr int GST = (4 * AH + 31) / 32 * 32 + NBH;
+};
+
+template <int N> struct KSmem {
+    using C = KCfg<N>;
+    static constexpr size_t win = (size_t)2 * C::WIN_DW * 4;
+    static constexpr size_t acc = (size_t)C::GPW * C::GST * 4;
+    static size_t dig(int R) { return (size_t)C::GPW * R * 3 * 2 * C::H; }
+    static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
+    static size_t total(int R, int n) { return win + acc + dig(R) + ms(n); }
+};
+
+__device__ __forceinline__ void kara_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ uint32_t kara_modswitch(uint32_t u, int log2_2n)
+{
+    return (u + (1u << (31 - log2_2n))) >> (32 - log2_2n);
+}
+
+// bsk [n][2l][2][N] -> half-length key windows [n][R][2][3][4][ELEN]:
+// window y of (i, r*S+s, c', P) holds limb q of h_ext[y - 31] * 2^(7s),
+// where h = a_e (P = 0), a_o (P = 1) or a_e - a_o (P = 2) of a = bsk[i][r]
+// [c'], h_ext[x] = h[x] (0 <= x < H), -h[x+H] (x < 0), 0 beyond H.
+template <int N>
+__global__ void k_kara_key(const uint32_t *__restrict__ bsk,
+                           int8_t *__restrict__ out, int n, int l, int S)
+{
+    using C = KCfg<N>;
+    constexpr int H = C::H;
+    const int R = 2 * l * S;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t total = (size_t)n * R * 2 * 3 * C::ELEN;
+    if (idx >= total)
+        return;
+    int y = (int)(idx % C::ELEN);
+    size_t t = idx / C::ELEN;
+    int P = (int)(t % 3);
+    t /= 3;
+    int cp = (int)(t % 2);
+    t /= 2;
+    int kb = (int)(t % R);
+    int i = (int)(t / R);
+    int r = kb / S, s = kb % S;
+    const uint32_t *a = bsk + (((size_t)i * 2 * l + r) * 2 + cp) * N;
+    auto half = [&](int x) -> uint32_t {
+        uint32_t e = a[2 * x], o = a[2 * x + 1];
+        return P == 0 ? e : (P == 1 ? o : e - o);
+    };
+    int x = y - 31;
+    uint32_t v = 0;
+    if (x >= 0 && x < H)
+        v = half(x);
+    else if (x < 0)
+        v = 0u - half(x + H);
+    v <<= 7 * s;
+    int8_t *o = out + ((((size_t)i * R + kb) * 2 + cp) * 3 + P) * 4 * C::ELEN + y;
+    for (int q = 0; q < 4; ++q) {
+        int8_t limb = (int8_t)(v & 0xFFu);
+        o[(size_t)q * C::ELEN] = limb;
+        v = (v - (uint32_t)(int32_t)limb) >> 8;
+    }
+}
+
+// L (gadget levels) and S (sub-digits per digit) are compile-time so the
+// digit loops unroll; L = 0 selects a generic build reading l and S at run
+// time (at most 8 levels, 2 sub-digits).
+template <int N, int L, int S>
+__global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
+    const int8_t *__restrict__ key, const uint32_t *__restrict__ in,
+    const uint32_t *__restrict__ testv, uint32_t *__restrict__ out, int B,
+    const int32_t *__restrict__ d_count, int lo, int hi, int n, int beta,
+    int l_rt, int S_rt)
+{
+    using C = KCfg<N>;
+    constexpr int H = C::H, NBH = C::NBH, BPT = C::BPT, GPW = C::GPW;
+    constexpr int THREADS = C::THREADS, EW = C::EW, WIN_DW = C::WIN_DW;
+    constexpr int AH = C::AH, GST = C::GST;
+    constexpr int LOG2_2N = __builtin_ctz(2 * N);
+    const int l = L ? L : l_rt;
+    const int SS = L ? S : S_rt;
+    const int R = 2 * l * SS;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t *win = reinterpret_cast<uint32_t *>(smem);          // [2][WIN_DW]
+    uint32_t *acc = win + 2 * WIN_DW;                             // [GPW][GST]
+    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * GST);    // [GPW][R][3][2][H]
+    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPW * R * 6 * H);
+
+    // a launch issued next to others for a count read on the device runs
+    // only when lo < count <= hi
+    const int dc = d_count ? *d_count : B;
+    if (dc <= lo || dc > hi)
+        return;
+    const int count = min(B, dc);
+    const int g0 = blockIdx.x * GPW;
+    if (g0 >= count)
+        return;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+
+    // accumulator word of coefficient j (0 <= j < N) of component c
+    auto aidx = [](int gl, int c, int j) {
+        const int h = j >> 1;
+        return gl * GST + c * 2 * AH + (j & 1) * AH + h + (h >> 5);
+    };
+
+    // ---- modulus switch of the inputs --------------------------------
+    for (int idx = tid; idx < GPW * (n + 1); idx += THREADS) {
+        int gl = idx / (n + 1), i = idx - gl * (n + 1);
+        int g = g0 + gl;
+        uint32_t u = g < count ? in[(size_t)g * (n + 1) + i] : 0u;
+        ms[idx] = (uint16_t)kara_modswitch(u, LOG2_2N);
+    }
+    __syncthreads();
+    // ---- ACC = (0, X^(2N - b~) v) ---------------------------------------
+    for (int idx = tid; idx < GPW * N; idx += THREADS) {
+        int gl = idx / N, m = idx - gl * N;
+        int e = (2 * N - ms[gl * (n + 1) + n]) & (2 * N - 1);
+        uint32_t v = testv ? testv[m] : (1u << 29);
+        int t = m + e;
+        if (t >= 2 * N) {
+            t -= 2 * N;
+        } else if (t >= N) {
+            t -= N;
+            v = 0u - v;
+        }
+        acc[aidx(gl, 0, t)] = 0u;
+        acc[aidx(gl, 1, t)] = v;
+    }
+
+    // ---- key-window staging: stage st = i*R + kb uses buffer st & 1 ------
+    constexpr int PER_T = (WIN_DW + THREADS - 1) / THREADS;
+    uint32_t pre[PER_T];
+    const uint32_t *key32 = reinterpret_cast<const uint32_t *>(key);
+    auto fetch = [&](int st) {
+        const uint32_t *src = key32 + (size_t)st * WIN_DW;
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+            const int item = tid + k * THREADS;
+            if (item < WIN_DW)
+                pre[k] = src[item];
+        }
+    };
+    auto stash = [&](int buf, int k) {
+#pragma unroll
+        for (int kk = 0; kk < PER_T; ++kk) {
+            const int item = tid + kk * THREADS;
+            if (kk == k && item < WIN_DW)
+                win[buf * WIN_DW + item] = pre[kk];
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+        stash(0, k);
+    if (n * R > 1)
+        fetch(1);
+    __syncthreads();
+
+    // ---- per-lane constants ----------------------------------------------
+    const int P = wave >> 2;                  // product: 0 e*e, 1 o*o, 2 diff
+    const int cp = wave & 1;                  // output component
+    const int q0 = 2 * ((wave >> 1) & 1);     // first key limb
+    const int rho = lane & 31, hh = lane >> 5;
+    const int colJ = rho % NBH, colb = rho / NBH;   // column -> block, bootstrap
+    // A operand: first dword and byte shift of this lane's Toeplitz row
+    const int a_w0 = 4 * hh + (rho >> 2), a_sh = rho & 3;
+
+    const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
+    uint32_t dig_off = round_off;
+    for (int p = 1; p <= l; ++p)
+        dig_off += (1u << (beta - 1)) << (32 - p * beta);
+    const uint32_t bmask = (1u << beta) - 1u;
+    const int32_t bhalf = 1 << (beta - 1);
+
+    kv16i Cacc[2][2];   // [tile][limb]
+
+    for (int i = 0; i < n; ++i) {
+        kara_barrier();   // ACC of the previous step complete
+        // ---- rotate, subtract, decompose into E, O and E - O operands -----
+        for (int item = tid; item < GPW * 2 * (N / 8); item += THREADS) {
+            const int gl = item / (2 * (N / 8));
+            const int rem = item - gl * (2 * (N / 8));
+            const int c = rem / (N / 8);
+            const int m0 = 8 * (rem - c * (N / 8));
+            const int e = ms[gl * (n + 1) + i];
+            uint32_t w8[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int t = (m0 + k - e) & (2 * N - 1);
+                uint32_t rv = acc[aidx(gl, c, t & (N - 1))];
+                rv = t >= N ? 0u - rv : rv;
+                w8[k] = rv - acc[aidx(gl, c, m0 + k)] + dig_off;
+            }
+            // half-length coefficients mh0 .. mh0+3; byte b of a dword holds
+            // coefficient mh0 + 3 - b (reversed kappa)
+            const int mh0 = m0 >> 1;
+            const int kp = 28 - (mh0 & 31), M = mh0 >> 5;
+            const int off = (kp >> 4) * (NBH * 16) + M * 16 + (kp & 15);
+            int8_t *gbase = dig + (size_t)gl * R * 6 * H + off;
+#pragma unroll
+            for (int p = 1; p <= (L ? L : 8); ++p) {
+                if (!L && p > l)
+                    break;
+                int32_t d[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    d[k] = (int32_t)((w8[k] >> (32 - p * beta)) & bmask) - bhalf;
+#pragma unroll
+                for (int s = 0; s < (L ? S : 2); ++s) {
+                    if (!L && s >= SS)
+                        break;
+                    int32_t sd[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        if (s == SS - 1) {
+                            sd[k] = d[k];
+                        } else {
+                            sd[k] = ((d[k] + 64) & 127) - 64;
+                            d[k] = (d[k] - sd[k]) >> 7;
+                        }
+                    }
+                    uint32_t pw[3] = {0, 0, 0}, nw[3] = {0, 0, 0};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int32_t ve = sd[2 * k], vo = sd[2 * k + 1];
+                        const int32_t vals[3] = {ve, vo, ve - vo};
+#pragma unroll
+                        for (int pp = 0; pp < 3; ++pp) {
+                            pw[pp] |= ((uint32_t)vals[pp] & 0xFFu) << (8 * (3 - k));
+                            nw[pp] |= ((uint32_t)(-vals[pp]) & 0xFFu) << (8 * (3 - k));
+                        }
+                    }
+                    const int kb = (c * l + (p - 1)) * SS + s;
+#pragma unroll
+                    for (int pp = 0; pp < 3; ++pp) {
+                        int8_t *base = gbase + ((size_t)kb * 3 + pp) * 2 * H;
+                        *reinterpret_cast<uint32_t *>(base) = pw[pp];
+                        *reinterpret_cast<uint32_t *>(base + H) = nw[pp];
+                    }
+                }
+            }
+        }
+        kara_barrier();
+
+        // ---- K loop: digit polynomials x block offsets ----------------------
+        auto stage = [&](const int kb, auto first_c) {
+            constexpr bool FIRST = decltype(first_c)::value;
+            const int st = i * R + kb;
+            const bool more = st + 1 < n * R;
+            if (more && st >= 1)
+                fetch(st + 1);
+            const uint32_t *wb = win + (st & 1) * WIN_DW +
+                                 ((cp * 3 + P) * 4 + q0) * EW + a_w0;
+            const int8_t *db[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                db[t] = dig + ((size_t)((t * BPT + colb) * R + kb) * 3 + P) * 2 * H +
+                        hh * (NBH * 16);
+            auto load_a = [&](int dl, kv4i (&af)[2]) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const uint32_t *ap = wb + q * EW + 8 * dl;
+                    uint32_t w5[5];
+#pragma unroll
+                    for (int k = 0; k < 5; ++k)
+                        w5[k] = ap[k];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        af[q][k] = (int)__builtin_amdgcn_alignbyte(w5[k + 1], w5[k],
+                                                                   a_sh);
+                }
+            };
+            auto load_b = [&](int dl, kv4i (&bf)[2]) {
+                const int Mb = (colJ - dl) & (NBH - 1);
+                const int sg = colJ < dl ? H : 0;
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    bf[t] = *reinterpret_cast<const kv4i *>(db[t] + sg + Mb * 16);
+            };
+            kv4i af[2][2], bf[2][2];
+            // block offset dl: its four MFMAs on register buffer b, with the
+            // operands of dl + 1 read into the other buffer in their issue
+            // shadows, and (between MFMA groups) one item of the next
+            // stage's key windows stored to LDS
+            auto group = [&](int dl, int b, bool zero_start) {
+                if (dl + 1 < NBH) {
+                    load_a(dl + 1, af[b ^ 1]);
+                    load_b(dl + 1, bf[b ^ 1]);
+                }
+                const kv16i zero = {};
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                            af[b][q], bf[b][t], zero_start ? zero : Cacc[t][q],
+                            0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0); // DS read
+                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0); // VALU
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                if (more && dl >= 4 && dl - 4 < PER_T)
+                    stash((st + 1) & 1, dl - 4);
+                __builtin_amdgcn_sched_barrier(0);
+            };
+            load_a(0, af[0]);
+            load_b(0, bf[0]);
+            group(0, 0, FIRST);   // the first stage starts the accumulators
+#pragma unroll 1
+            for (int dl = 1; dl + 1 < NBH; dl += 2) {
+                group(dl, 1, false);
+                group(dl + 1, 0, false);
+            }
+            group(NBH - 1, 1, false);
+            if (more && NBH < PER_T + 4) {
+                for (int k = NBH - 4 > 0 ? NBH - 4 : 0; k < PER_T; ++k)
+                    stash((st + 1) & 1, k);
+            }
+            kara_barrier();
+        };
+        stage(0, std::true_type{});
+        for (int kb = 1; kb < R; ++kb)
+            stage(kb, std::false_type{});
+
+        // ---- fold limbs and products into ACC -------------------------------
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int gl = t * BPT + colb;
+            uint32_t *ae = acc + gl * GST + cp * 2 * AH;   // even half
+            uint32_t *ao = ae + AH;                        // odd half
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = 8 * (v >> 2) + 4 * hh + (v & 3);
+                const int m = 32 * colJ + row;
+                const uint32_t x = (((uint32_t)Cacc[t][0][v]) +
+                                    ((uint32_t)Cacc[t][1][v] << 8)) << (8 * q0);
+                const int pm = m + (m >> 5);
+                if (P == 0) {
+                    atomicAdd(&ae[pm], x);
+                    atomicAdd(&ao[pm], x);
+                } else if (P == 1) {
+                    atomicAdd(&ao[pm], x);
+                    if (m + 1 < H) {
+                        const int m1 = m + 1;
+                        atomicAdd(&ae[m1 + (m1 >> 5)], x);
+                    } else {
+                        atomicAdd(&ae[0], 0u - x);
+                    }
+                } else {
+                    atomicAdd(&ao[pm], 0u - x);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- sample extraction ---------------------------------------------------
+    for (int idx = tid; idx < GPW * (N + 1); idx += THREADS) {
+        int gl = idx / (N + 1), j = idx - gl * (N + 1);
+        int g = g0 + gl;
+        if (g >= count)
+            continue;
+        uint32_t v;
+        if (j == 0)
+            v = acc[aidx(gl, 0, 0)];
+        else if (j < N)
+            v = 0u - acc[aidx(gl, 0, N - j)];
+        else
+            v = acc[aidx(gl, 1, 0)];
+        out[(size_t)g * (N + 1) + j] = v;
+    }
+}
+
+template <int N, int L, int S>
+int kara_launch_t(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                  uint32_t *out, int B, const int32_t *d_count, int lo, int hi,
+                  hipStream_t s)
+{
+    using C = KCfg<N>;
+    const Shape &sh = c->sh;
+    const size_t smem = KSmem<N>::total(sh.R, sh.n);
+    const int grid = (B + C::GPW - 1) / C::GPW;
+    hipLaunchKernelGGL((k_bootstrap_int8_kara<N, L, S>), dim3(grid),
+                       dim3(C::THREADS), smem, s, c->bsk_k8, in, testv, out,
+                       B, d_count, lo, hi, sh.n, sh.beta, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    return CGGI_OK;
+}
+
+template <int N>
+int kara_launch_n(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                  uint32_t *out, int B, const int32_t *d_count, int lo, int hi,
+                  hipStream_t s)
+{
+    const Shape &sh = c->sh;
+    if (sh.l == 3 && sh.S == 1)
+        return kara_launch_t<N, 3, 1>(c, in, testv, out, B, d_count, lo, hi, s);
+    if (sh.l == 2 && sh.S == 2)
+        return kara_launch_t<N, 2, 2>(c, in, testv, out, B, d_count, lo, hi, s);
+    return kara_launch_t<N, 0, 0>(c, in, testv, out, B, d_count, lo, hi, s);
+}
+
+template <int N, int L, int S>
+int kara_attr_t()
+{
+    CGGI_HIP_TRY(hipFuncSetAttribute(
+        reinterpret_cast<const void *>(&k_bootstrap_int8_kara<N, L, S>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    return CGGI_OK;
+}
+
+template <int N>
+int kara_make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
+{
+    using C = KCfg<N>;
+    const Shape &sh = c->sh;
+    if (KSmem<N>::total(sh.R, sh.n) > 160 * 1024)
+        return CGGI_OK;                  // this kernel kind is unavailable
+    const size_t total = (size_t)sh.n * sh.R * 2 * 3 * C::ELEN;
+    if (hipMalloc(&c->bsk_k8, total * 4) != hipSuccess) {
+        c->bsk_k8 = nullptr;
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the Karatsuba int8 key "
+                                       "failed");
+    }
+    hipLaunchKernelGGL(k_kara_key<N>, dim3((unsigned)((total + 255) / 256)),
+                       dim3(256), 0, s, bsk, c->bsk_k8, sh.n, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    int rc;
+    if (sh.l == 3 && sh.S == 1)
+        rc = kara_attr_t<N, 3, 1>();
+    else if (sh.l == 2 && sh.S == 2)
+        rc = kara_attr_t<N, 2, 2>();
+    else
+        rc = kara_attr_t<N, 0, 0>();
+    return rc;
+}
+
+} // namespace
+
+size_t kara_smem_bytes(int N, int R, int n)
+{
+    switch (N) {
+    case 256: return KSmem<256>::total(R, n);
+    case 512: return KSmem<512>::total(R, n);
+    case 1024: return KSmem<1024>::total(R, n);
+    default: return (size_t)-1;
+    }
+}
+
+int kara_bootstraps_per_workgroup(int N)
+{
+    switch (N) {
+    case 256: return KCfg<256>::GPW;
+    case 512: return KCfg<512>::GPW;
+    case 1024: return KCfg<1024>::GPW;
+    default: return 0;
+    }
+}
+
+int kara_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s)
+{
+    switch (c->sh.N) {
+    case 256: return kara_make_key_n<256>(c, bsk, s);
+    case 512: return kara_make_key_n<512>(c, bsk, s);
+    case 1024: return kara_make_key_n<1024>(c, bsk, s);
+    default: return CGGI_OK;             // N = 2048: not available
+    }
+}
+
+int kara_launch(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                uint32_t *out, int B, const int32_t *d_count, int lo, int hi,
+                hipStream_t s)
+{
+    switch (c->sh.N) {
+    case 256: return kara_launch_n<256>(c, in, testv, out, B, d_count, lo, hi, s);
+    case 512: return kara_launch_n<512>(c, in, testv, out, B, d_count, lo, hi, s);
+    case 1024: return kara_launch_n<1024>(c, in, testv, out, B, d_count, lo, hi, s);
+    default: return set_error(CGGI_E_PARAM, "Karatsuba kernel: N > 1024");
+    }
+}
+
+} // namespace cggi

@@ -39,6 +39,9 @@ struct cggi_ctx {
     // INT8 form
     int8_t *bsk_i8 = nullptr;     // [n][R][2][4][elen] limb windows
     uint32_t *corr_i8 = nullptr;  // [n][2][N] digit-offset correction (N <= 1024)
+    // Karatsuba kernel: half-length key windows [n][R][2][3][4][N/2+64]
+    // (N <= 1024 and LDS permitting; null otherwise)
+    int8_t *bsk_k8 = nullptr;
     // INT8 latency mode (one tile over G = 8, 4 or 2 workgroups, N <= 1024);
     // index 0: G = 4, index 1: G = 2, index 2: G = 8
     bool split_on = true;         // cggi_ctx_latency_mode
@@ -55,7 +58,7 @@ struct cggi_ctx {
     int plan_n = 0;
     int32_t plan_kind[8] = {};
     int32_t plan_cap[8] = {};
-    int64_t kind_limit[6] = {0, 0, 0, 0, 0, 0};
+    int64_t kind_limit[7] = {0, 0, 0, 0, 0, 0, 0};
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
     int ks_ksj = 0;               // 32-slot K-steps per j
@@ -103,6 +106,13 @@ int int8_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s);
 int int8_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
                    uint32_t *out, int B, const int32_t *d_count,
                    hipStream_t s);
+// Karatsuba kernel (int8_kara.hip): key windows at context creation (a
+// no-op where the kernel is unavailable), and a launch over B bootstraps
+// (device count in (lo, hi] when d_count is given).
+int kara_make_key(Ctx *c, const uint32_t *bsk, hipStream_t s);
+int kara_launch(const Ctx *c, const uint32_t *in, const uint32_t *testv,
+                uint32_t *out, int B, const int32_t *d_count, int lo, int hi,
+                hipStream_t s);
 // Re-zeroes the latency-mode exchange buffers, epochs and error word
 // (synchronous).
 int int8_split_reset(Ctx *c);

@@ -1,8 +1,9 @@
 """Autotuner of the int8 form's kernel plan (and of the form per level width).
 
-The int8 form has six kernels for a batch of bootstraps (cggi.KINDS):
-latency mode with eight, four or two workgroups per column tile, and one
-workgroup per 1, 2 or 4 column tiles.  All give bit-identical results; which is
+The int8 form has seven kernels for a batch of bootstraps (cggi.KINDS):
+latency mode with eight, four or two workgroups per column tile, one
+workgroup per 1, 2 or 4 column tiles, and the Karatsuba kernel (three
+half-length products per negacyclic product).  All give bit-identical results; which is
 fastest depends on the batch width, the parameter set and the GPU.  The
 tuner times every kernel that can take each width of a grid (one
 cggi_bootstrap_batch per measurement under a plan that forces the kernel,

@@ -19,6 +19,24 @@ def test_int8_ops_default_and_large():
         2 * 4096 * (4 * 2048 * 2) * 4 * 742
 
 
+def test_int8_ops_karatsuba_and_kernel_lookup():
+    # three half-length products: 3 * 2 * 2(N/2) * (2l(N/2) * S) * 4 * n
+    full = bench.int8_ops_per_bootstrap(params.DEFAULT)
+    assert bench.int8_ops_per_bootstrap(params.DEFAULT, "kara2") == \
+        3 * 2 * 1024 * (6 * 512) * 4 * 630 == full * 3 // 4
+    plan = [("split8", 16), ("tiles1", 256), ("tiles2", 512),
+            ("kara2", 2**31 - 1)]
+    assert bench.int8_kind_for(plan, 1) == "split8"
+    assert bench.int8_kind_for(plan, 512) == "tiles2"
+    assert bench.int8_kind_for(plan, 1024) == "kara2"
+    assert bench.int8_kernel_name(params.DEFAULT, "kara2") == \
+        "k_bootstrap_int8_kara<1024, 3, 1>"
+    assert bench.int8_kernel_name(params.DEFAULT, "tiles4") == \
+        "k_bootstrap_int8<1024, 3, 1, 4>"
+    assert bench.int8_kernel_name(params.LARGE, "tiles4") == \
+        "k_bootstrap_int8<2048, 2, 2, 4>"
+
+
 def test_ntt_mulmods_default():
     # (2l + 2) transforms of N/2 log2 N butterflies + 2l * 2N pointwise
     assert bench.ntt_mulmods_per_bootstrap(params.DEFAULT) == \

@@ -73,9 +73,10 @@ def test_params_bootstrap_and_keyswitch_bit_exact(O, p):
         assert np.array_equal(cggi.to_host(out), want), (p.name, form)
     # the built-in plan sends this batch to latency mode; every throughput
     # kernel (one, two and four tiles per workgroup; the four-tile one with
-    # offset digit operands) on the same full workgroup + ragged tail
+    # offset digit operands; the Karatsuba kernel where its workgroup fits
+    # the LDS) on the same full workgroup + ragged tail
     limits = ctx.int8_limits()
-    for kind in ("tiles1", "tiles2", "tiles4"):
+    for kind in ("tiles1", "tiles2", "tiles4", "kara2"):
         if limits[kind] < B:
             continue
         say(f"params {p.name} int8 kernel {kind} B={B}")
