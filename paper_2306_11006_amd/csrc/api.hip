@@ -121,6 +121,7 @@ static void free_ctx(Ctx *c)
     (void)hipFree(c->bsk_i8);
     (void)hipFree(c->corr_i8);
     (void)hipFree(c->bsk_k8);
+    (void)hipFree(c->corr_k8);
     for (int v = 0; v < 3; ++v) {
         (void)hipFree(c->x_buf[v]);
         (void)hipFree(c->x_epoch[v]);

@@ -24,6 +24,21 @@ __host__ __device__ __forceinline__ uint64_t add(uint64_t a, uint64_t b)
     return r;
 }
 
+// a + b for any a < 2^64 and a canonical b < Q, left in [0, 2^64) rather
+// than reduced to [0, Q): after a carry out of 2^64 the sum is below
+// 2^64 + Q, so adding 2^64 mod Q = 2^32 - 1 cannot carry again.  The
+// Cooley-Tukey butterflies use it (their V is always a fresh product); a
+// product, or sub with a canonical subtrahend, takes such a value as is.
+__host__ __device__ __forceinline__ uint64_t add_lazy(uint64_t a, uint64_t b)
+{
+    uint64_t r = a + b;
+    if (r < a)
+        r += EPS;
+    return r;
+}
+
+// a - b for a canonical b (a anything below 2^64): on a borrow the result
+// a - b + Q lies in (0, Q), otherwise a - b < 2^64.
 __host__ __device__ __forceinline__ uint64_t sub(uint64_t a, uint64_t b)
 {
     uint64_t r = a - b;

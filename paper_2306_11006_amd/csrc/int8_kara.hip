@@ -33,7 +33,12 @@
 //   and odd[m];  P3 -> minus odd[m].
 // The accumulator is stored de-interleaved (even and odd halves, each row
 // padded by one dword per 32 so the fold's lanes fall in distinct banks).
-// Digit operands live in LDS in both signs (for the wrapped blocks), key
+// Digit operands live in LDS in both signs (for the wrapped blocks); the E
+// and O operands are stored offset (delta + 64 and 63 - delta, both in
+// [0, 127]: non-negative operands cost the matrix cores less energy) and
+// the P1 and P2 accumulators of limb 0 start from minus the offsets'
+// contribution, a function of the key only (k_kara_corr); E - O stays
+// signed.  Key
 // windows (one byte-exact copy per stage, double-buffered, prefetched from
 // global memory a stage ahead) are read as five aligned dwords per lane and
 // byte-aligned in registers.
@@ -68,7 +73,15 @@ template <int N> struct KSmem {
     using C = KCfg<N>;
     static constexpr size_t win = (size_t)2 * C::WIN_DW * 4;
     static constexpr size_t acc = (size_t)C::GPW * C::GST * 4;
-    static size_t dig(int R) { return (size_t)C::GPW * R * 3 * 2 * C::H; }
+    // digit operands; after a step's last stage the same bytes stage the
+    // fold's partial sums (3 products x 2 components x 2 tiles x 1024
+    // entries of 4 + 2 bytes), so the area is at least that large
+    __host__ __device__ static size_t dig(int R)
+    {
+        const size_t d = (size_t)C::GPW * R * 3 * 2 * C::H;
+        return d > STG ? d : STG;
+    }
+    static constexpr size_t STG = (size_t)3 * 2 * 2 * 1024 * 6;
     static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
     static size_t total(int R, int n) { return win + acc + dig(R) + ms(n); }
 };
@@ -129,15 +142,83 @@ __global__ void k_kara_key(const uint32_t *__restrict__ bsk,
     }
 }
 
+// Offset correction of the E and O operands.  With the positive copy
+// holding delta + 64 and the negated copy 63 - delta, the half-length GEMM
+// of product P (0: a_e with E, 1: a_o with O) exceeds the product at
+// coefficient m = 32J + rho by
+//   sum over digit rows of (63 * total[rho] + head_J[rho]),
+// W_Delta[rho] = sum_kappa h_ext[32 Delta + rho - kappa] * 2^(7s) the row
+// sum of Toeplitz block Delta of that row's half key h, total = the sum over
+// every Delta, head_J = the sum over Delta <= J (blocks read from the
+// positive copy).  corr [n][2][2][H] (step, c', P, m) holds that excess mod
+// 2^32.  One workgroup per (i, c', P).
+template <int N>
+__global__ __launch_bounds__(256) void k_kara_corr(
+    const uint32_t *__restrict__ bsk, uint32_t *__restrict__ corr, int n,
+    int l, int S)
+{
+    constexpr int H = N / 2, NBH = H / 32, PT = (H + 255) / 256;
+    __shared__ uint32_t ext[H + 32];   // ext[x + 31] = h_ext[x], -31 <= x < H
+    __shared__ uint32_t W[H];          // W_Delta[rho] at 32 Delta + rho
+    const int i = blockIdx.x >> 2, cp = (blockIdx.x >> 1) & 1;
+    const int P = blockIdx.x & 1;
+    if (i >= n)
+        return;
+    const int tid = threadIdx.x;
+    const int R = 2 * l * S;
+    uint32_t accv[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k)
+        accv[k] = 0u;
+    for (int kb = 0; kb < R; ++kb) {
+        const int r = kb / S, s = kb - r * S;
+        const uint32_t *a = bsk + (((size_t)i * 2 * l + r) * 2 + cp) * N;
+        for (int x = tid - 31; x < H; x += 256)
+            ext[x + 31] = x >= 0 ? a[2 * x + P] : 0u - a[2 * (x + H) + P];
+        __syncthreads();
+        for (int t = tid; t < H; t += 256) {
+            uint32_t w = 0;
+            for (int kap = 0; kap < 32; ++kap)
+                w += ext[t - kap + 31];
+            W[t] = w;
+        }
+        __syncthreads();
+        if (tid < 32) {                // prefix over Delta, per rho
+            uint32_t run = 0;
+            for (int D = 0; D < NBH; ++D) {
+                run += W[32 * D + tid];
+                W[32 * D + tid] = run;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PT; ++k) {
+            const int j = tid + 256 * k;
+            if (j < H) {
+                const int J = j >> 5, rho = j & 31;
+                const uint32_t total = W[32 * (NBH - 1) + rho];
+                accv[k] += (63u * total + W[32 * J + rho]) << (7 * s);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+        const int j = tid + 256 * k;
+        if (j < H)
+            corr[(((size_t)i * 2 + cp) * 2 + P) * H + j] = accv[k];
+    }
+}
+
 // L (gadget levels) and S (sub-digits per digit) are compile-time so the
 // digit loops unroll; L = 0 selects a generic build reading l and S at run
 // time (at most 8 levels, 2 sub-digits).
 template <int N, int L, int S>
 __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
-    const int8_t *__restrict__ key, const uint32_t *__restrict__ in,
-    const uint32_t *__restrict__ testv, uint32_t *__restrict__ out, int B,
-    const int32_t *__restrict__ d_count, int lo, int hi, int n, int beta,
-    int l_rt, int S_rt)
+    const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
+    const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
+    uint32_t *__restrict__ out, int B, const int32_t *__restrict__ d_count,
+    int lo, int hi, int n, int beta, int l_rt, int S_rt)
 {
     using C = KCfg<N>;
     constexpr int H = C::H, NBH = C::NBH, BPT = C::BPT, GPW = C::GPW;
@@ -152,7 +233,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);          // [2][WIN_DW]
     uint32_t *acc = win + 2 * WIN_DW;                             // [GPW][GST]
     int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * GST);    // [GPW][R][3][2][H]
-    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + (size_t)GPW * R * 6 * H);
+    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + KSmem<N>::dig(R));
 
     // a launch issued next to others for a count read on the device runs
     // only when lo < count <= hi
@@ -166,7 +247,9 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    // wave index as a scalar: everything derived from it is wave-uniform
+    // wave index as a scalar: everything derived from it is wave-uniform
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // accumulator word of coefficient j (0 <= j < N) of component c
     auto aidx = [](int gl, int c, int j) {
@@ -198,35 +281,6 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
         acc[aidx(gl, 1, t)] = v;
     }
 
-    // ---- key-window staging: stage st = i*R + kb uses buffer st & 1 ------
-    constexpr int PER_T = (WIN_DW + THREADS - 1) / THREADS;
-    uint32_t pre[PER_T];
-    const uint32_t *key32 = reinterpret_cast<const uint32_t *>(key);
-    auto fetch = [&](int st) {
-        const uint32_t *src = key32 + (size_t)st * WIN_DW;
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k) {
-            const int item = tid + k * THREADS;
-            if (item < WIN_DW)
-                pre[k] = src[item];
-        }
-    };
-    auto stash = [&](int buf, int k) {
-#pragma unroll
-        for (int kk = 0; kk < PER_T; ++kk) {
-            const int item = tid + kk * THREADS;
-            if (kk == k && item < WIN_DW)
-                win[buf * WIN_DW + item] = pre[kk];
-        }
-    };
-    fetch(0);
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k)
-        stash(0, k);
-    if (n * R > 1)
-        fetch(1);
-    __syncthreads();
-
     // ---- per-lane constants ----------------------------------------------
     const int P = wave >> 2;                  // product: 0 e*e, 1 o*o, 2 diff
     const int cp = wave & 1;                  // output component
@@ -235,6 +289,43 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int colJ = rho % NBH, colb = rho / NBH;   // column -> block, bootstrap
     // A operand: first dword and byte shift of this lane's Toeplitz row
     const int a_w0 = 4 * hh + (rho >> 2), a_sh = rho & 3;
+    // the wave that starts the offset correction of its product (P1, P2)
+    const bool corr_wave = P < 2 && q0 == 0;
+
+    // ---- key-window staging: stage st = i*R + kb uses buffer st & 1 ------
+    // Each wave reads only the windows of its own (c', P, limb pair): two
+    // contiguous limb windows per stage, which it stages itself into its
+    // own double buffer, so no barrier separates the stages.
+    constexpr int WW = 2 * EW;                        // dwords per wave slice
+    constexpr int PER_W = (WW + 63) / 64;
+    uint32_t pre[PER_W];
+    uint32_t *winw = win + wave * (2 * WW);
+    const uint32_t *key32 = reinterpret_cast<const uint32_t *>(key) +
+                            ((cp * 3 + P) * 4 + q0) * EW;
+    auto fetch = [&](int st) {
+        const uint32_t *src = key32 + (size_t)st * WIN_DW;
+#pragma unroll
+        for (int k = 0; k < PER_W; ++k) {
+            const int item = lane + 64 * k;
+            if (item < WW)
+                pre[k] = src[item];
+        }
+    };
+    auto stash = [&](int buf, int k) {
+#pragma unroll
+        for (int kk = 0; kk < PER_W; ++kk) {
+            const int item = lane + 64 * kk;
+            if (kk == k && item < WW)
+                winw[buf * WW + item] = pre[kk];
+        }
+    };
+    fetch(0);
+#pragma unroll
+    for (int k = 0; k < PER_W; ++k)
+        stash(0, k);
+    if (n * R > 1)
+        fetch(1);
+    __syncthreads();
 
     const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
     uint32_t dig_off = round_off;
@@ -247,6 +338,20 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
 
     for (int i = 0; i < n; ++i) {
         kara_barrier();   // ACC of the previous step complete
+        // limb-0 accumulators of P1 / P2 start from minus the step's offset
+        // correction (the same for both tiles: it depends on the key only)
+        kv16i cinit = {};
+        if (corr_wave) {
+            const uint32_t *cr = corr + (((size_t)i * 2 + cp) * 2 + P) * H +
+                                 32 * colJ + 4 * hh;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const kv4i c4 = *reinterpret_cast<const kv4i *>(cr + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    cinit[4 * g + e] = -c4[e];
+            }
+        }
         // ---- rotate, subtract, decompose into E, O and E - O operands -----
         for (int item = tid; item < GPW * 2 * (N / 8); item += THREADS) {
             const int gl = item / (2 * (N / 8));
@@ -268,46 +373,63 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const int kp = 28 - (mh0 & 31), M = mh0 >> 5;
             const int off = (kp >> 4) * (NBH * 16) + M * 16 + (kp & 15);
             int8_t *gbase = dig + (size_t)gl * R * 6 * H + off;
+            // four offset sub-digits v = delta + 64 in [0, 128) -> one dword
+            auto pack4 = [](uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+                return (a << 24) | (b << 16) | (c << 8) | d;
+            };
+            // one digit row: E and O offset (delta + 64 and, negated,
+            // 63 - delta = 127 - (delta + 64)); E - O signed, formed per
+            // byte without borrows: (E' | 0x80) - O' = E - O + 128 in
+            // [1, 255], then the top bit flipped
+            auto emit = [&](int kb, const uint32_t (&v)[8]) {
+                const uint32_t pe = pack4(v[0], v[2], v[4], v[6]);
+                const uint32_t po = pack4(v[1], v[3], v[5], v[7]);
+                const uint32_t pw[3] = {
+                    pe, po, ((pe | 0x80808080u) - po) ^ 0x80808080u};
+                const uint32_t nw[3] = {
+                    pe ^ 0x7F7F7F7Fu, po ^ 0x7F7F7F7Fu,
+                    ((po | 0x80808080u) - pe) ^ 0x80808080u};
+#pragma unroll
+                for (int pp = 0; pp < 3; ++pp) {
+                    int8_t *base = gbase + ((size_t)kb * 3 + pp) * 2 * H;
+                    *reinterpret_cast<uint32_t *>(base) = pw[pp];
+                    *reinterpret_cast<uint32_t *>(base + H) = nw[pp];
+                }
+            };
 #pragma unroll
             for (int p = 1; p <= (L ? L : 8); ++p) {
                 if (!L && p > l)
                     break;
+                const int sh = 32 - p * beta;
+                if (SS == 1) {
+                    // one sub-digit: delta + 64 = ((w >> sh) & (Bg-1)) - Bg/2 + 64
+                    uint32_t v[8];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k)
+                        v[k] = ((w8[k] >> sh) & bmask) + (uint32_t)(64 - bhalf);
+                    emit(c * l + (p - 1), v);
+                    continue;
+                }
                 int32_t d[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
-                    d[k] = (int32_t)((w8[k] >> (32 - p * beta)) & bmask) - bhalf;
+                    d[k] = (int32_t)((w8[k] >> sh) & bmask) - bhalf;
 #pragma unroll
                 for (int s = 0; s < (L ? S : 2); ++s) {
                     if (!L && s >= SS)
                         break;
-                    int32_t sd[8];
+                    uint32_t v[8];
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
                         if (s == SS - 1) {
-                            sd[k] = d[k];
+                            v[k] = (uint32_t)(d[k] + 64);
                         } else {
-                            sd[k] = ((d[k] + 64) & 127) - 64;
-                            d[k] = (d[k] - sd[k]) >> 7;
+                            // low 7-bit sub-digit delta = v - 64 in [-64, 64)
+                            v[k] = (uint32_t)(d[k] + 64) & 127u;
+                            d[k] = (d[k] + 64 - (int32_t)v[k]) >> 7;
                         }
                     }
-                    uint32_t pw[3] = {0, 0, 0}, nw[3] = {0, 0, 0};
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int32_t ve = sd[2 * k], vo = sd[2 * k + 1];
-                        const int32_t vals[3] = {ve, vo, ve - vo};
-#pragma unroll
-                        for (int pp = 0; pp < 3; ++pp) {
-                            pw[pp] |= ((uint32_t)vals[pp] & 0xFFu) << (8 * (3 - k));
-                            nw[pp] |= ((uint32_t)(-vals[pp]) & 0xFFu) << (8 * (3 - k));
-                        }
-                    }
-                    const int kb = (c * l + (p - 1)) * SS + s;
-#pragma unroll
-                    for (int pp = 0; pp < 3; ++pp) {
-                        int8_t *base = gbase + ((size_t)kb * 3 + pp) * 2 * H;
-                        *reinterpret_cast<uint32_t *>(base) = pw[pp];
-                        *reinterpret_cast<uint32_t *>(base + H) = nw[pp];
-                    }
+                    emit((c * l + (p - 1)) * SS + s, v);
                 }
             }
         }
@@ -320,8 +442,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const bool more = st + 1 < n * R;
             if (more && st >= 1)
                 fetch(st + 1);
-            const uint32_t *wb = win + (st & 1) * WIN_DW +
-                                 ((cp * 3 + P) * 4 + q0) * EW + a_w0;
+            const uint32_t *wb = winw + (st & 1) * WW + a_w0;
             const int8_t *db[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t)
@@ -364,7 +485,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
 #pragma unroll
                     for (int q = 0; q < 2; ++q)
                         Cacc[t][q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                            af[b][q], bf[b][t], zero_start ? zero : Cacc[t][q],
+                            af[b][q], bf[b][t],
+                            zero_start ? (q == 0 ? cinit : zero) : Cacc[t][q],
                             0, 0, 0);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
@@ -373,7 +495,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                     __builtin_amdgcn_sched_group_barrier(0x002, 3, 0); // VALU
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                if (more && dl >= 4 && dl - 4 < PER_T)
+                if (more && dl >= 4 && dl - 4 < PER_W)
                     stash((st + 1) & 1, dl - 4);
                 __builtin_amdgcn_sched_barrier(0);
             };
@@ -386,44 +508,68 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                 group(dl + 1, 0, false);
             }
             group(NBH - 1, 1, false);
-            if (more && NBH < PER_T + 4) {
-                for (int k = NBH - 4 > 0 ? NBH - 4 : 0; k < PER_T; ++k)
+            if (more && NBH < PER_W + 4) {
+                for (int k = NBH - 4 > 0 ? NBH - 4 : 0; k < PER_W; ++k)
                     stash((st + 1) & 1, k);
             }
-            kara_barrier();
         };
         stage(0, std::true_type{});
         for (int kb = 1; kb < R; ++kb)
             stage(kb, std::false_type{});
 
-        // ---- fold limbs and products into ACC -------------------------------
+        kara_barrier();   // every wave done with the digit operands
+
+        // ---- fold: partial sums -> staging -> accumulator --------------------
+        // Each wave's two limbs recombined (C_q0 + C_q0+1 * 2^8; the wave of
+        // limbs 2, 3 keeps the low 16 bits, which is all its 2^16-scaled sum
+        // needs) go to staging in the (now idle) digit area without atomics;
+        // then every thread owns some (bootstrap, component, m) and adds
+        //   even[m] += P1[m] + P2[m-1]   (P2[-1] = -P2[H-1], Z^(N/2) = -1)
+        //   odd[m]  += P1[m] + P2[m]  - P3[m]
+        // Staging entry of (bootstrap b of a tile, m = 32J + rho): b H + 32 J
+        // + (rho ^ (J + NBH b)), so the 32 lanes of one write hit distinct
+        // banks.
+        uint32_t *stg32 = reinterpret_cast<uint32_t *>(dig);
+        uint16_t *stg16 = reinterpret_cast<uint16_t *>(stg32 + 3 * 2 * 2 * 1024);
+        auto sidx = [](int b, int m) {
+            const int J = m >> 5, r = m & 31;
+            return b * H + 32 * J + (r ^ (J + NBH * b));
+        };
+        // this lane's staging base and swizzle, made opaque per step so the
+        // 32 entry addresses are formed here rather than kept live (and
+        // spilled) across the whole step loop
+        int s_base = colb * H + 32 * colJ, s_swz = colJ + NBH * colb;
+        asm volatile("" : "+v"(s_base), "+v"(s_swz));
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int gl = t * BPT + colb;
-            uint32_t *ae = acc + gl * GST + cp * 2 * AH;   // even half
-            uint32_t *ao = ae + AH;                        // odd half
+            const int sb = ((P * 2 + cp) * 2 + t) * 1024 + s_base;
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int row = 8 * (v >> 2) + 4 * hh + (v & 3);
-                const int m = 32 * colJ + row;
-                const uint32_t x = (((uint32_t)Cacc[t][0][v]) +
-                                    ((uint32_t)Cacc[t][1][v] << 8)) << (8 * q0);
-                const int pm = m + (m >> 5);
-                if (P == 0) {
-                    atomicAdd(&ae[pm], x);
-                    atomicAdd(&ao[pm], x);
-                } else if (P == 1) {
-                    atomicAdd(&ao[pm], x);
-                    if (m + 1 < H) {
-                        const int m1 = m + 1;
-                        atomicAdd(&ae[m1 + (m1 >> 5)], x);
-                    } else {
-                        atomicAdd(&ae[0], 0u - x);
-                    }
-                } else {
-                    atomicAdd(&ao[pm], 0u - x);
-                }
+                const int e = sb + (row ^ s_swz);
+                const uint32_t x = (uint32_t)Cacc[t][0][v] +
+                                   ((uint32_t)Cacc[t][1][v] << 8);
+                if (q0 == 0)
+                    stg32[e] = x;
+                else
+                    stg16[e] = (uint16_t)x;
             }
+        }
+        kara_barrier();
+        for (int item = tid; item < GPW * 2 * H; item += THREADS) {
+            const int gl = item / (2 * H);
+            const int rem = item - gl * (2 * H);
+            const int c = rem / H, m = rem - c * H;
+            const int t = gl / BPT, b = gl - t * BPT;
+            auto part = [&](int pr, int mm) {
+                const int e = ((pr * 2 + c) * 2 + t) * 1024 + sidx(b, mm);
+                return stg32[e] + ((uint32_t)stg16[e] << 16);
+            };
+            const uint32_t x1 = part(0, m), x2 = part(1, m), x3 = part(2, m);
+            const uint32_t x2p = m > 0 ? part(1, m - 1) : 0u - part(1, H - 1);
+            uint32_t *a = acc + gl * GST + c * 2 * AH + m + (m >> 5);
+            a[0] += x1 + x2p;
+            a[AH] += x1 + x2 - x3;
         }
     }
     __syncthreads();
@@ -455,8 +601,9 @@ int kara_launch_t(const Ctx *c, const uint32_t *in, const uint32_t *testv,
     const size_t smem = KSmem<N>::total(sh.R, sh.n);
     const int grid = (B + C::GPW - 1) / C::GPW;
     hipLaunchKernelGGL((k_bootstrap_int8_kara<N, L, S>), dim3(grid),
-                       dim3(C::THREADS), smem, s, c->bsk_k8, in, testv, out,
-                       B, d_count, lo, hi, sh.n, sh.beta, sh.l, sh.S);
+                       dim3(C::THREADS), smem, s, c->bsk_k8, c->corr_k8, in,
+                       testv, out, B, d_count, lo, hi, sh.n, sh.beta, sh.l,
+                       sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     return CGGI_OK;
 }
@@ -498,6 +645,15 @@ int kara_make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
     }
     hipLaunchKernelGGL(k_kara_key<N>, dim3((unsigned)((total + 255) / 256)),
                        dim3(256), 0, s, bsk, c->bsk_k8, sh.n, sh.l, sh.S);
+    CGGI_HIP_TRY(hipGetLastError());
+    const size_t cbytes = (size_t)sh.n * 2 * 2 * C::H * sizeof(uint32_t);
+    if (hipMalloc(&c->corr_k8, cbytes) != hipSuccess) {
+        c->corr_k8 = nullptr;
+        return set_error(CGGI_E_NOMEM, "hipMalloc of the Karatsuba offset "
+                                       "correction failed");
+    }
+    hipLaunchKernelGGL(k_kara_corr<N>, dim3(4 * sh.n), dim3(256), 0, s, bsk,
+                       c->corr_k8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     int rc;
     if (sh.l == 3 && sh.S == 1)

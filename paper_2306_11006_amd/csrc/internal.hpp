@@ -42,6 +42,7 @@ struct cggi_ctx {
     // Karatsuba kernel: half-length key windows [n][R][2][3][4][N/2+64]
     // (N <= 1024 and LDS permitting; null otherwise)
     int8_t *bsk_k8 = nullptr;
+    uint32_t *corr_k8 = nullptr;  // [n][2][2][N/2] its digit-offset correction
     // INT8 latency mode (one tile over G = 8, 4 or 2 workgroups, N <= 1024);
     // index 0: G = 4, index 1: G = 2, index 2: G = 8
     bool split_on = true;         // cggi_ctx_latency_mode

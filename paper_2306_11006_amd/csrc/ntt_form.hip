@@ -65,8 +65,9 @@ __device__ __forceinline__ void fwd_block(uint64_t (&v)[1 << NS], int m0, int i,
             if (k & d)
                 continue;
             const uint64_t S = tw[(m0 << u) + (i << u) + (k >> (NS - u))];
+            // V is a canonical product, so U may stay unreduced
             const uint64_t U = v[k], V = gl::mul(v[k + d], S);
-            v[k] = gl::add(U, V);
+            v[k] = gl::add_lazy(U, V);
             v[k + d] = gl::sub(U, V);
         }
     }
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
             for (int r = 0; r < L2; ++r) {
                 const uint64_t U = dig[(size_t)r * N + 2 * j];
                 const uint64_t V = gl::mul(dig[(size_t)r * N + 2 * j + 1], S);
-                const uint64_t x0 = gl::add(U, V), x1 = gl::sub(U, V);
+                const uint64_t x0 = gl::add_lazy(U, V), x1 = gl::sub(U, V);
 #pragma unroll
                 for (int cp = 0; cp < 2; ++cp) {
                     const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(
