@@ -63,6 +63,10 @@ template <int N> struct KCfg {
     static constexpr int ELEN = H + 64;      // bytes per key window
     static constexpr int EW = ELEN / 4;      // dwords per key window
     static constexpr int WIN_DW = 2 * 3 * 4 * EW;  // one stage: c', P, limb
+    // one byte-shifted copy of a window in LDS: the A reads of a stage touch
+    // dwords up to 8 NBH + 6; the stride is = 8 (mod 32) dwords, so the
+    // four copies one read touches fall in distinct banks
+    static constexpr int CLEN = (8 * NBH + 7 + 23) / 32 * 32 + 8;
     static constexpr int AH = H + H / 32;    // padded accumulator half
     // dwords per bootstrap's accumulators (2 components x 2 halves), = NBH
     // mod 32 so that the bootstraps of a tile land on distinct banks
@@ -71,7 +75,8 @@ template <int N> struct KCfg {
 
 template <int N> struct KSmem {
     using C = KCfg<N>;
-    static constexpr size_t win = (size_t)2 * C::WIN_DW * 4;
+    // per wave: 2 limbs x 4 byte-shifted copies, single-buffered
+    static constexpr size_t win = (size_t)12 * 2 * 4 * C::CLEN * 4;
     static constexpr size_t acc = (size_t)C::GPW * C::GST * 4;
     // digit operands; after a step's last stage the same bytes stage the
     // fold's partial sums (3 products x 2 components x 2 tiles x 1024
@@ -82,8 +87,7 @@ template <int N> struct KSmem {
         return d > STG ? d : STG;
     }
     static constexpr size_t STG = (size_t)3 * 2 * 2 * 1024 * 6;
-    static size_t ms(int n) { return ((size_t)C::GPW * (n + 1) * 2 + 15) & ~(size_t)15; }
-    static size_t total(int R, int n) { return win + acc + dig(R) + ms(n); }
+    static size_t total(int R, int n) { (void)n; return win + acc + dig(R); }
 };
 
 __device__ __forceinline__ void kara_barrier()
@@ -230,10 +234,10 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int R = 2 * l * SS;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    uint32_t *win = reinterpret_cast<uint32_t *>(smem);          // [2][WIN_DW]
-    uint32_t *acc = win + 2 * WIN_DW;                             // [GPW][GST]
+    constexpr int CLEN = C::CLEN;
+    uint32_t *win = reinterpret_cast<uint32_t *>(smem);  // [12][2][4][CLEN]
+    uint32_t *acc = win + 12 * 2 * 4 * CLEN;              // [GPW][GST]
     int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * GST);    // [GPW][R][3][2][H]
-    uint16_t *ms = reinterpret_cast<uint16_t *>(dig + KSmem<N>::dig(R));
 
     // a launch issued next to others for a count read on the device runs
     // only when lo < count <= hi
@@ -257,18 +261,17 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
         return gl * GST + c * 2 * AH + (j & 1) * AH + h + (h >> 5);
     };
 
-    // ---- modulus switch of the inputs --------------------------------
-    for (int idx = tid; idx < GPW * (n + 1); idx += THREADS) {
-        int gl = idx / (n + 1), i = idx - gl * (n + 1);
-        int g = g0 + gl;
-        uint32_t u = g < count ? in[(size_t)g * (n + 1) + i] : 0u;
-        ms[idx] = (uint16_t)kara_modswitch(u, LOG2_2N);
-    }
-    __syncthreads();
+    // modulus-switched input coefficient i of bootstrap gl (read from
+    // global memory where needed; 0 past the batch)
+    auto msw = [&](int gl, int i) -> int {
+        const int g = g0 + gl;
+        const uint32_t u = g < count ? in[(size_t)g * (n + 1) + i] : 0u;
+        return (int)kara_modswitch(u, LOG2_2N);
+    };
     // ---- ACC = (0, X^(2N - b~) v) ---------------------------------------
     for (int idx = tid; idx < GPW * N; idx += THREADS) {
         int gl = idx / N, m = idx - gl * N;
-        int e = (2 * N - ms[gl * (n + 1) + n]) & (2 * N - 1);
+        int e = (2 * N - msw(gl, n)) & (2 * N - 1);
         uint32_t v = testv ? testv[m] : (1u << 29);
         int t = m + e;
         if (t >= 2 * N) {
@@ -288,41 +291,52 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int rho = lane & 31, hh = lane >> 5;
     const int colJ = rho % NBH, colb = rho / NBH;   // column -> block, bootstrap
     // A operand: first dword and byte shift of this lane's Toeplitz row
-    const int a_w0 = 4 * hh + (rho >> 2), a_sh = rho & 3;
+    const int a_w0 = (rho & 3) * CLEN + 4 * hh + (rho >> 2);
     // the wave that starts the offset correction of its product (P1, P2)
     const bool corr_wave = P < 2 && q0 == 0;
 
-    // ---- key-window staging: stage st = i*R + kb uses buffer st & 1 ------
-    // Each wave reads only the windows of its own (c', P, limb pair): two
-    // contiguous limb windows per stage, which it stages itself into its
-    // own double buffer, so no barrier separates the stages.
-    constexpr int WW = 2 * EW;                        // dwords per wave slice
-    constexpr int PER_W = (WW + 63) / 64;
-    uint32_t pre[PER_W];
-    uint32_t *winw = win + wave * (2 * WW);
+    // ---- key-window staging ------------------------------------------------
+    // Each wave reads only the windows of its own (c', P, limb pair) and
+    // stages them itself: the two limb windows of the next stage are read
+    // from global memory a stage ahead, and between two stages the wave
+    // writes them to its own LDS buffer as four byte-shifted copies (copy
+    // sigma, dword w = window bytes 4w + sigma .. 4w + sigma + 3), so each
+    // lane reads its 16-byte Toeplitz row as four aligned dwords.  LDS
+    // operations of one wave complete in order, so no barrier is needed.
+    constexpr int CI = 2 * CLEN;                      // copy dwords per slice
+    constexpr int PER_W = (CI + 63) / 64;
+    uint32_t pre_lo[PER_W], pre_hi[PER_W];
+    uint32_t *winw = win + wave * (2 * 4 * CLEN);     // [limb][sigma][CLEN]
     const uint32_t *key32 = reinterpret_cast<const uint32_t *>(key) +
                             ((cp * 3 + P) * 4 + q0) * EW;
     auto fetch = [&](int st) {
         const uint32_t *src = key32 + (size_t)st * WIN_DW;
 #pragma unroll
         for (int k = 0; k < PER_W; ++k) {
-            const int item = lane + 64 * k;
-            if (item < WW)
-                pre[k] = src[item];
+            // every lane loads (a clamped item re-reads a valid word it
+            // does not store)
+            const int item = min(lane + 64 * k, CI - 1);
+            const int q = item / CLEN, w = item - q * CLEN;
+            pre_lo[k] = src[q * EW + w];
+            pre_hi[k] = src[q * EW + w + 1];
         }
     };
-    auto stash = [&](int buf, int k) {
+    auto stash = [&]() {
 #pragma unroll
-        for (int kk = 0; kk < PER_W; ++kk) {
-            const int item = lane + 64 * kk;
-            if (kk == k && item < WW)
-                winw[buf * WW + item] = pre[kk];
+        for (int k = 0; k < PER_W; ++k) {
+            const int item = lane + 64 * k;
+            if (item < CI) {
+                const int q = item / CLEN, w = item - q * CLEN;
+                uint32_t *d = winw + q * 4 * CLEN + w;
+                d[0] = pre_lo[k];
+                d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
+                d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
+                d[3 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
+            }
         }
     };
     fetch(0);
-#pragma unroll
-    for (int k = 0; k < PER_W; ++k)
-        stash(0, k);
+    stash();
     if (n * R > 1)
         fetch(1);
     __syncthreads();
@@ -358,7 +372,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const int rem = item - gl * (2 * (N / 8));
             const int c = rem / (N / 8);
             const int m0 = 8 * (rem - c * (N / 8));
-            const int e = ms[gl * (n + 1) + i];
+            const int e = msw(gl, i);
             uint32_t w8[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
@@ -442,7 +456,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const bool more = st + 1 < n * R;
             if (more && st >= 1)
                 fetch(st + 1);
-            const uint32_t *wb = winw + (st & 1) * WW + a_w0;
+            const uint32_t *wb = winw + a_w0;
             const int8_t *db[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t)
@@ -451,15 +465,10 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             auto load_a = [&](int dl, kv4i (&af)[2]) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const uint32_t *ap = wb + q * EW + 8 * dl;
-                    uint32_t w5[5];
-#pragma unroll
-                    for (int k = 0; k < 5; ++k)
-                        w5[k] = ap[k];
+                    const uint32_t *ap = wb + q * 4 * CLEN + 8 * dl;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        af[q][k] = (int)__builtin_amdgcn_alignbyte(w5[k + 1], w5[k],
-                                                                   a_sh);
+                        af[q][k] = (int)ap[k];
                 }
             };
             auto load_b = [&](int dl, kv4i (&bf)[2]) {
@@ -495,9 +504,6 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                     __builtin_amdgcn_sched_group_barrier(0x002, 3, 0); // VALU
                 }
                 __builtin_amdgcn_sched_barrier(0);
-                if (more && dl >= 4 && dl - 4 < PER_W)
-                    stash((st + 1) & 1, dl - 4);
-                __builtin_amdgcn_sched_barrier(0);
             };
             load_a(0, af[0]);
             load_b(0, bf[0]);
@@ -508,10 +514,10 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                 group(dl + 1, 0, false);
             }
             group(NBH - 1, 1, false);
-            if (more && NBH < PER_W + 4) {
-                for (int k = NBH - 4 > 0 ? NBH - 4 : 0; k < PER_W; ++k)
-                    stash((st + 1) & 1, k);
-            }
+            // the next stage's windows replace this one's (every read of
+            // this stage was issued before these writes)
+            if (more)
+                stash();
         };
         stage(0, std::true_type{});
         for (int kb = 1; kb < R; ++kb)
