@@ -63,10 +63,12 @@ template <int N> struct KCfg {
     static constexpr int ELEN = H + 64;      // bytes per key window
     static constexpr int EW = ELEN / 4;      // dwords per key window
     static constexpr int WIN_DW = 2 * 3 * 4 * EW;  // one stage: c', P, limb
-    // one byte-shifted copy of a window in LDS: the A reads of a stage touch
-    // dwords up to 8 NBH + 6; the stride is = 8 (mod 32) dwords, so the
-    // four copies one read touches fall in distinct banks
-    static constexpr int CLEN = (8 * NBH + 7 + 23) / 32 * 32 + 8;
+    // one byte-shifted copy of a limb window in LDS: the A reads of a stage
+    // touch dwords up to 8 NBH + 6.  Copies are laid out [sigma][limb]
+    // [CLEN] with CLEN = 12 (mod 16): the two limbs of one copy are CLEN
+    // dwords apart (one ds_read2 reaches both), and the copy stride 2 CLEN =
+    // 24 (mod 32) puts the four copies one read touches in distinct banks
+    static constexpr int CLEN = (8 * NBH + 7 - 12 + 15) / 16 * 16 + 12;
     static constexpr int AH = H + H / 32;    // padded accumulator half
     // dwords per bootstrap's accumulators (2 components x 2 halves), = NBH
     // mod 32 so that the bootstraps of a tile land on distinct banks
@@ -291,7 +293,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int rho = lane & 31, hh = lane >> 5;
     const int colJ = rho % NBH, colb = rho / NBH;   // column -> block, bootstrap
     // A operand: first dword and byte shift of this lane's Toeplitz row
-    const int a_w0 = (rho & 3) * CLEN + 4 * hh + (rho >> 2);
+    const int a_w0 = (rho & 3) * 2 * CLEN + 4 * hh + (rho >> 2);
     // the wave that starts the offset correction of its product (P1, P2)
     const bool corr_wave = P < 2 && q0 == 0;
 
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     constexpr int CI = 2 * CLEN;                      // copy dwords per slice
     constexpr int PER_W = (CI + 63) / 64;
     uint32_t pre_lo[PER_W], pre_hi[PER_W];
-    uint32_t *winw = win + wave * (2 * 4 * CLEN);     // [limb][sigma][CLEN]
+    uint32_t *winw = win + wave * (2 * 4 * CLEN);     // [sigma][limb][CLEN]
     const uint32_t *key32 = reinterpret_cast<const uint32_t *>(key) +
                             ((cp * 3 + P) * 4 + q0) * EW;
     auto fetch = [&](int st) {
@@ -327,11 +329,11 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const int item = lane + 64 * k;
             if (item < CI) {
                 const int q = item / CLEN, w = item - q * CLEN;
-                uint32_t *d = winw + q * 4 * CLEN + w;
+                uint32_t *d = winw + q * CLEN + w;
                 d[0] = pre_lo[k];
-                d[CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
-                d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
-                d[3 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
+                d[2 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 1);
+                d[4 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 2);
+                d[6 * CLEN] = __builtin_amdgcn_alignbyte(pre_hi[k], pre_lo[k], 3);
             }
         }
     };
@@ -457,32 +459,37 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             if (more && st >= 1)
                 fetch(st + 1);
             const uint32_t *wb = winw + a_w0;
-            const int8_t *db[2];
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-                db[t] = dig + ((size_t)((t * BPT + colb) * R + kb) * 3 + P) * 2 * H +
-                        hh * (NBH * 16);
+            // B: this lane's 16 bytes of digit block (J - Delta) mod NBH of
+            // tile 0 (tile 1 lies TS bytes further), from the negated copy
+            // when the block index wrapped (J < Delta).  The block offset
+            // costs a compare, a select and an add per block offset; tile 1
+            // is an immediate offset.
+            const int TS = BPT * R * 6 * H;
+            // (an opaque lane offset, so that the digit area's own offset is
+            // folded into the base rather than into every read's immediate)
+            int boff = ((colb * R + kb) * 3 + P) * 2 * H + hh * (NBH * 16) +
+                       16 * colJ - 16 * (NBH - 1);
+            asm volatile("" : "+v"(boff));
+            const int8_t *bb = dig + boff;
             auto load_a = [&](int dl, kv4i (&af)[2]) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const uint32_t *ap = wb + q * 4 * CLEN + 8 * dl;
+                    const uint32_t *ap = wb + q * CLEN + 8 * dl;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
                         af[q][k] = (int)ap[k];
                 }
             };
             auto load_b = [&](int dl, kv4i (&bf)[2]) {
-                const int Mb = (colJ - dl) & (NBH - 1);
-                const int sg = colJ < dl ? H : 0;
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-                    bf[t] = *reinterpret_cast<const kv4i *>(db[t] + sg + Mb * 16);
+                const int8_t *pb = bb + (colJ < dl ? NBH * 16 + H : 0) +
+                                   16 * (NBH - 1 - dl);
+                bf[0] = *reinterpret_cast<const kv4i *>(pb);
+                bf[1] = *reinterpret_cast<const kv4i *>(pb + TS);
             };
             kv4i af[2][2], bf[2][2];
             // block offset dl: its four MFMAs on register buffer b, with the
             // operands of dl + 1 read into the other buffer in their issue
-            // shadows, and (between MFMA groups) one item of the next
-            // stage's key windows stored to LDS
+            // shadows
             auto group = [&](int dl, int b, bool zero_start) {
                 if (dl + 1 < NBH) {
                     load_a(dl + 1, af[b ^ 1]);
@@ -501,7 +508,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                 for (int k = 0; k < 4; ++k) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
                     __builtin_amdgcn_sched_group_barrier(0x100, 3, 0); // DS read
-                    __builtin_amdgcn_sched_group_barrier(0x002, 3, 0); // VALU
+                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0); // VALU
                 }
                 __builtin_amdgcn_sched_barrier(0);
             };
