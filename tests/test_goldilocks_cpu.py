@@ -5,7 +5,9 @@ add, the unreduced add_lazy of the Cooley-Tukey butterflies, sub and the
 1, Q - 1, the unreduced range [Q, 2^64), 2^64 - 1, values next to 2^32 and
 2^63) and seeded random words.  add_lazy must stay below 2^64 for every
 a < 2^64 and canonical b and agree with a + b mod Q; sub must do the same
-for any a and canonical b.  Compiled with hipcc; the checks run on the
+for any a and canonical b.  The reduction is also driven through its wrap
+corrections: low words just below, at and above the high word's top half
+(the subtraction borrows) and high words with every half-word edge.  Compiled with hipcc; the checks run on the
 host (the header's host/device functions), no GPU needed."""
 import os
 import shutil
@@ -47,6 +49,24 @@ int main() {
             if ((u128)sub(a, b) % Q != wsub) ++bad;
             if (a < Q && sub(a, b) >= Q) ++bad;
             uint64_t hi = a, lo = rnd();
+            u128 x = ((u128)hi << 64) | lo;
+            uint64_t r = reduce128(hi, lo);
+            if (r >= Q || (u128)r != x % Q) ++bad;
+            n += 1;
+        }
+    }
+    // reduce128's wrap corrections: low words below the high word's top
+    // half (borrow), high words whose low half shifted up carries, both.
+    std::vector<uint64_t> L = {0, 1, 2, 0xFFFFFFFEull, 0xFFFFFFFFull,
+        0x100000000ull, Q - 1, Q, ~0ull, ~0ull - 0xFFFFFFFFull};
+    for (size_t i = 0; i < A.size(); ++i) {
+        const uint64_t hi = A[i], h1 = hi >> 32;
+        uint64_t los[16] = {h1 - 1, h1, h1 + 1, rnd() >> 40, rnd() % (h1 + 1)};
+        int nl = 5;
+        if (i < 64)
+            for (uint64_t v : L) los[nl++ % 16] = v;
+        for (int k = 0; k < nl && k < 16; ++k) {
+            const uint64_t lo = los[k];
             u128 x = ((u128)hi << 64) | lo;
             uint64_t r = reduce128(hi, lo);
             if (r >= Q || (u128)r != x % Q) ++bad;
