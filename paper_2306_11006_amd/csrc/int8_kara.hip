@@ -239,7 +239,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     constexpr int CLEN = C::CLEN;
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);  // [12][2][4][CLEN]
     uint32_t *acc = win + 12 * 2 * 4 * CLEN;              // [GPW][GST]
-    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * GST);    // [GPW][R][3][2][H]
+    // digit operands [GPW][R][3][kappa half][sign: -, +][NBH][16]
+    int8_t *dig = reinterpret_cast<int8_t *>(acc + GPW * GST);
 
     // a launch issued next to others for a count read on the device runs
     // only when lo < count <= hi
@@ -387,7 +388,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             // coefficient mh0 + 3 - b (reversed kappa)
             const int mh0 = m0 >> 1;
             const int kp = 28 - (mh0 & 31), M = mh0 >> 5;
-            const int off = (kp >> 4) * (NBH * 16) + M * 16 + (kp & 15);
+            const int off = (kp >> 4) * (2 * NBH * 16) + M * 16 + (kp & 15);
             int8_t *gbase = dig + (size_t)gl * R * 6 * H + off;
             // four offset sub-digits v = delta + 64 in [0, 128) -> one dword
             auto pack4 = [](uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
@@ -408,8 +409,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
 #pragma unroll
                 for (int pp = 0; pp < 3; ++pp) {
                     int8_t *base = gbase + ((size_t)kb * 3 + pp) * 2 * H;
-                    *reinterpret_cast<uint32_t *>(base) = pw[pp];
-                    *reinterpret_cast<uint32_t *>(base + H) = nw[pp];
+                    *reinterpret_cast<uint32_t *>(base + NBH * 16) = pw[pp];
+                    *reinterpret_cast<uint32_t *>(base) = nw[pp];
                 }
             };
 #pragma unroll
@@ -461,14 +462,15 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const uint32_t *wb = winw + a_w0;
             // B: this lane's 16 bytes of digit block (J - Delta) mod NBH of
             // tile 0 (tile 1 lies TS bytes further), from the negated copy
-            // when the block index wrapped (J < Delta).  The block offset
-            // costs a compare, a select and an add per block offset; tile 1
-            // is an immediate offset.
+            // when the block index wrapped (J < Delta).  Each kappa half of a
+            // digit row holds the negated blocks followed by the blocks, so
+            // both cases are block NBH + J - Delta of that row: one base per
+            // lane and an immediate offset per block offset and tile.
             const int TS = BPT * R * 6 * H;
             // (an opaque lane offset, so that the digit area's own offset is
             // folded into the base rather than into every read's immediate)
-            int boff = ((colb * R + kb) * 3 + P) * 2 * H + hh * (NBH * 16) +
-                       16 * colJ - 16 * (NBH - 1);
+            int boff = ((colb * R + kb) * 3 + P) * 2 * H +
+                       hh * (2 * NBH * 16) + 16 * colJ + 16;
             asm volatile("" : "+v"(boff));
             const int8_t *bb = dig + boff;
             auto load_a = [&](int dl, kv4i (&af)[2]) {
@@ -481,8 +483,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                 }
             };
             auto load_b = [&](int dl, kv4i (&bf)[2]) {
-                const int8_t *pb = bb + (colJ < dl ? NBH * 16 + H : 0) +
-                                   16 * (NBH - 1 - dl);
+                const int8_t *pb = bb + 16 * (NBH - 1 - dl);
                 bf[0] = *reinterpret_cast<const kv4i *>(pb);
                 bf[1] = *reinterpret_cast<const kv4i *>(pb + TS);
             };
@@ -505,11 +506,11 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                             zero_start ? (q == 0 ? cinit : zero) : Cacc[t][q],
                             0, 0, 0);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
+                for (int k = 0; k < 3; ++k) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x100, 3, 0); // DS read
-                    __builtin_amdgcn_sched_group_barrier(0x002, 1, 0); // VALU
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0); // DS read
                 }
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                 __builtin_amdgcn_sched_barrier(0);
             };
             load_a(0, af[0]);
