@@ -73,9 +73,6 @@ template <int N> struct KCfg {
     // dwords per bootstrap's accumulators (2 components x 2 halves), = NBH
     // mod 32 so that the bootstraps of a tile land on distinct banks
     static constexpr int GST = (4 * AH + 31) / 32 * 32 + NBH;
-    // fold staging entries per (product, component, tile): the tile's BPT
-    // bootstraps, each padded like an accumulator half (= 32 * 33)
-    static constexpr int SE = BPT * AH;
 };
 
 template <int N> struct KSmem {
@@ -83,15 +80,11 @@ template <int N> struct KSmem {
     // per wave: 2 limbs x 4 byte-shifted copies, single-buffered
     static constexpr size_t win = (size_t)12 * 2 * 4 * C::CLEN * 4;
     static constexpr size_t acc = (size_t)C::GPW * C::GST * 4;
-    // digit operands; after a step's last stage the same bytes stage the
-    // fold's partial sums (3 products x 2 components x 2 tiles x SE
-    // entries of 4 + 2 bytes), so the area is at least that large
+    // digit operands
     __host__ __device__ static size_t dig(int R)
     {
-        const size_t d = (size_t)C::GPW * R * 3 * 2 * C::H;
-        return d > STG ? d : STG;
+        return (size_t)C::GPW * R * 3 * 2 * C::H;
     }
-    static constexpr size_t STG = (size_t)3 * 2 * 2 * C::SE * 6;
     static size_t total(int R, int n) { (void)n; return win + acc + dig(R); }
 };
 
@@ -355,12 +348,6 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int32_t bhalf = 1 << (beta - 1);
 
     kv16i Cacc[2][2];   // [tile][limb]
-    // fold staging in the digit area: 32-bit sums of limbs 0, 1, then the
-    // low 16 bits of those of limbs 2, 3
-    constexpr int SE = C::SE;
-    uint32_t *stg32 = reinterpret_cast<uint32_t *>(dig);
-    uint16_t *stg16 = reinterpret_cast<uint16_t *>(stg32 + 3 * 2 * 2 * SE);
-    const int l_pad = lane + (lane >> 5);   // lane's padded chunk offset
 
     for (int i = 0; i < n; ++i) {
         kara_barrier();   // ACC of the previous step complete
@@ -540,69 +527,66 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
         for (int kb = 1; kb < R; ++kb)
             stage(kb, std::false_type{});
 
-        kara_barrier();   // every wave done with the digit operands
-
-        // ---- fold: partial sums -> staging -> accumulator --------------------
-        // Each wave's two limbs recombined (C_q0 + C_q0+1 * 2^8; the wave of
-        // limbs 2, 3 keeps the low 16 bits, which is all its 2^16-scaled sum
-        // needs) go to staging in the (now idle) digit area without atomics;
-        // then each wave takes 64-coefficient chunks of the accumulator rows
-        // (bootstrap, component) and adds
-        //   even[m] += P1[m] + P2[m-1]   (P2[-1] = -P2[H-1], Z^(N/2) = -1)
-        //   odd[m]  += P1[m] + P2[m]  - P3[m]
-        // Staging entry of (product, component, tile, bootstrap b of the
-        // tile, m): ((pr * 2 + c) * 2 + t) SE + b AH + m + (m >> 5), one pad
-        // word per 32 like the accumulator, so that the 32 lanes of one
-        // write (m = 32 J + rho, J and b from the lane's column) fall in
-        // distinct banks and every write is the lane's base plus an
-        // immediate.
+        // ---- fold: each wave adds its sums straight into the accumulator ----
+        // The wave's two limbs recombined, C_q0 + C_q0+1 * 2^8, times 2^(8 q0)
+        // (limbs 2, 3 only matter mod 2^16), go into the accumulator with
+        // LDS atomic adds as soon as the wave's K loop ends:
+        //   P1[m] -> even[m] and odd[m]
+        //   P2[m] -> even[m+1] (minus even[0] for m = H-1, Z^(N/2) = -1) and
+        //            odd[m]
+        //   P3[m] -> minus odd[m]
+        // Nothing reads the accumulator until the next step's decomposition,
+        // after its barrier, and the adds commute mod 2^32, so the waves of
+        // the products that finish first fold while the others still run.
+        // Lane (colJ, colb, hh) holds m = 32 colJ + 8 g + 4 hh + k of
+        // bootstrap t BPT + colb (value v = 4 g + k of tile t), at padded
+        // index 33 colJ + 8 g + 4 hh + k: a lane base plus an immediate.
         {
-            const int st_lane = ((P * 2 + cp) * 2) * SE + colb * AH +
-                                (32 + 1) * colJ + 4 * hh;
-            if (q0 == 0) {
-                uint32_t *d = stg32 + st_lane;
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v)
-                        d[t * SE + 8 * (v >> 2) + (v & 3)] =
-                            (uint32_t)Cacc[t][0][v] +
-                            ((uint32_t)Cacc[t][1][v] << 8);
-            } else {
-                uint16_t *d = stg16 + st_lane;
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int v = 0; v < 16; ++v)
-                        d[t * SE + 8 * (v >> 2) + (v & 3)] = (uint16_t)(
-                            (uint32_t)Cacc[t][0][v] +
-                            ((uint32_t)Cacc[t][1][v] << 8));
-            }
-        }
-        kara_barrier();
-        // 64 chunks per workgroup (GPW x 2 rows of H / 64), round robin over
-        // the waves; everything but the lane offset is wave-uniform
-        for (int task = wave; task < GPW * 2 * (H / 64); task += THREADS / 64) {
-            const int row = task / (H / 64), m0 = 64 * (task % (H / 64));
-            const int gl = row >> 1, c = row & 1;
-            const int t = gl / BPT, b = gl - t * BPT;
-            const int srow = (c * 2 + t) * SE + b * AH;
-            const int e = srow + m0 + (m0 >> 5) + l_pad;
-            // P2 at m - 1: the previous padded entry (two back across a pad
-            // word); for m = 0 the row's last entry, negated
-            const bool wrap = m0 == 0 && lane == 0;
-            const int ep = wrap ? srow + (H - 1) + ((H - 1) >> 5)
-                                : e - 1 - ((lane & 31) == 0);
-            auto part = [&](int pr, int x) {
-                return stg32[x + pr * 4 * SE] +
-                       ((uint32_t)stg16[x + pr * 4 * SE] << 16);
+            uint32_t *ab = acc + colb * GST + cp * 2 * AH + 33 * colJ + 4 * hh;
+            auto add = [](uint32_t *x, uint32_t v) {
+                __hip_atomic_fetch_add(x, v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             };
-            const uint32_t x1 = part(0, e), x2 = part(1, e), x3 = part(2, e);
-            uint32_t x2p = part(1, ep);
-            x2p = wrap ? 0u - x2p : x2p;
-            uint32_t *a = acc + gl * GST + c * 2 * AH + m0 + (m0 >> 5) + l_pad;
-            a[0] += x1 + x2p;
-            a[AH] += x1 + x2 - x3;
+            // P2's even[m + 1] for the lane's last row (m = 32 colJ + 31 on
+            // hh = 1): the next block's first entry, or minus even[0] of
+            // the same bootstrap after the last block
+            const bool top = hh == 1 && colJ == NBH - 1;
+            const int last_off = hh == 0 ? 1 : (top ? -(33 * colJ + 31) : 2);
+            const int sh = 8 * q0;
+            // one straight-line body per product (the product is
+            // wave-uniform; a test per value would cost scalar branches)
+            auto fold = [&](auto prod) {
+                constexpr int PR = decltype(prod)::value;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    uint32_t *at = ab + t * BPT * GST;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const uint32_t x =
+                            ((uint32_t)Cacc[t][0][v] +
+                             ((uint32_t)Cacc[t][1][v] << 8)) << sh;
+                        uint32_t *e = at + 8 * (v >> 2) + (v & 3);
+                        if (PR == 0) {
+                            add(e, x);
+                            add(e + AH, x);
+                        } else if (PR == 1) {
+                            add(e + AH, x);
+                            if (v == 15)
+                                add(e + last_off, top ? 0u - x : x);
+                            else
+                                add(e + 1, x);
+                        } else {
+                            add(e + AH, 0u - x);
+                        }
+                    }
+                }
+            };
+            if (P == 0)
+                fold(std::integral_constant<int, 0>{});
+            else if (P == 1)
+                fold(std::integral_constant<int, 1>{});
+            else
+                fold(std::integral_constant<int, 2>{});
         }
     }
     __syncthreads();
