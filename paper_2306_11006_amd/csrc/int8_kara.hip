@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void k_kara_corr(
 // L (gadget levels) and S (sub-digits per digit) are compile-time so the
 // digit loops unroll; L = 0 selects a generic build reading l and S at run
 // time (at most 8 levels, 2 sub-digits).
-template <int N, int L, int S>
+template <int N, int L, int S, int BB>
 __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int8_t *__restrict__ key, const uint32_t *__restrict__ corr,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
@@ -340,12 +340,30 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
         fetch(1);
     __syncthreads();
 
-    const uint32_t round_off = (beta * l < 32) ? (1u << (31 - beta * l)) : 0u;
+    // digit width log2(Bg): a constant where the launch fixes it
+    const int bt = BB ? BB : beta;
+    const uint32_t round_off = (bt * l < 32) ? (1u << (31 - bt * l)) : 0u;
     uint32_t dig_off = round_off;
     for (int p = 1; p <= l; ++p)
-        dig_off += (1u << (beta - 1)) << (32 - p * beta);
-    const uint32_t bmask = (1u << beta) - 1u;
-    const int32_t bhalf = 1 << (beta - 1);
+        dig_off += (1u << (bt - 1)) << (32 - p * bt);
+    const uint32_t bmask = (1u << bt) - 1u;
+    const int32_t bhalf = 1 << (bt - 1);
+
+    // The decomposition works in 64-item chunks (item: 8 consecutive
+    // coefficients of one component of one bootstrap); a chunk lies in one
+    // bootstrap, so the step's rotation is wave-uniform.  Each wave reads
+    // the rotations of the next step during the current one.
+    constexpr int ROWI = N / 8, GLI = 2 * ROWI, NCH = GPW * GLI / 64;
+    constexpr int CPW = (NCH + THREADS / 64 - 1) / (THREADS / 64);
+    int e_cur[CPW], e_nxt[CPW];
+    auto load_e = [&](int ii, int (&dst)[CPW]) {
+#pragma unroll
+        for (int it = 0; it < CPW; ++it) {
+            const int ch = wave + (THREADS / 64) * it;
+            dst[it] = ch < NCH ? msw(ch * 64 / GLI, ii) : 0;
+        }
+    };
+    load_e(0, e_cur);
 
     kv16i Cacc[2][2];   // [tile][limb]
 
@@ -366,19 +384,42 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             }
         }
         // ---- rotate, subtract, decompose into E, O and E - O operands -----
-        for (int item = tid; item < GPW * 2 * (N / 8); item += THREADS) {
-            const int gl = item / (2 * (N / 8));
-            const int rem = item - gl * (2 * (N / 8));
-            const int c = rem / (N / 8);
-            const int m0 = 8 * (rem - c * (N / 8));
-            const int e = msw(gl, i);
+#pragma unroll
+        for (int it = 0; it < CPW; ++it) {
+            const int ch = wave + (THREADS / 64) * it;
+            if (ch >= NCH)
+                break;
+            const int gl = ch * 64 / GLI;
+            const int rem = ch * 64 - gl * GLI + lane;
+            const int c = rem / ROWI;
+            const int m0 = 8 * (rem - c * ROWI);
+            // In halves (even E, odd O; h = m >> 1) with e = 2 f + pe, the
+            // rotation X^(-e) reads E[h - f] and O[h - f] (pe = 0) or
+            // O[h - f - 1] and E[h - f] (pe = 1) for the even and odd
+            // coefficients; a half index u < 0 wraps to u + H with the sign
+            // flipped per wrap (Z^H = -1): bit log2(H) of u.
+            const int e = e_cur[it];
+            const int f = e >> 1, pe = e & 1;
+            const int h0 = m0 >> 1;
+            const uint32_t *Ec = acc + gl * GST + c * 2 * AH;
+            const uint32_t *Oc = Ec + AH;
+            const uint32_t *srcE = pe ? Oc : Ec;
+            const uint32_t *srcO = pe ? Ec : Oc;
+            const int uE = h0 - f - pe, uO = h0 - f;
+            const uint32_t *sE = Ec + h0 + (h0 >> 5);   // 4 unrotated entries
+            auto rot = [&](const uint32_t *src, int u) {
+                const int x = u & (H - 1);
+                const uint32_t v = src[x + (x >> 5)];
+                // all ones when bit log2(H) of u is set
+                const uint32_t mk = (uint32_t)__builtin_amdgcn_sbfe(
+                    u, __builtin_ctz(H), 1);
+                return (v ^ mk) - mk;
+            };
             uint32_t w8[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const int t = (m0 + k - e) & (2 * N - 1);
-                uint32_t rv = acc[aidx(gl, c, t & (N - 1))];
-                rv = t >= N ? 0u - rv : rv;
-                w8[k] = rv - acc[aidx(gl, c, m0 + k)] + dig_off;
+            for (int kk = 0; kk < 4; ++kk) {
+                w8[2 * kk] = rot(srcE, uE + kk) - sE[kk] + dig_off;
+                w8[2 * kk + 1] = rot(srcO, uO + kk) - sE[AH + kk] + dig_off;
             }
             // half-length coefficients mh0 .. mh0+3; byte b of a dword holds
             // coefficient mh0 + 3 - b (reversed kappa)
@@ -413,7 +454,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             for (int p = 1; p <= (L ? L : 8); ++p) {
                 if (!L && p > l)
                     break;
-                const int sh = 32 - p * beta;
+                const int sh = 32 - p * bt;
                 if (SS == 1) {
                     // one sub-digit: delta + 64 = ((w >> sh) & (Bg-1)) - Bg/2 + 64
                     uint32_t v[8];
@@ -447,6 +488,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             }
         }
         kara_barrier();
+        if (i + 1 < n)
+            load_e(i + 1, e_nxt);
 
         // ---- K loop: digit polynomials x block offsets ----------------------
         auto stage = [&](const int kb, auto first_c) {
@@ -588,6 +631,9 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             else
                 fold(std::integral_constant<int, 2>{});
         }
+#pragma unroll
+        for (int it = 0; it < CPW; ++it)
+            e_cur[it] = e_nxt[it];
     }
     __syncthreads();
 
@@ -608,7 +654,7 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     }
 }
 
-template <int N, int L, int S>
+template <int N, int L, int S, int BB>
 int kara_launch_t(const Ctx *c, const uint32_t *in, const uint32_t *testv,
                   uint32_t *out, int B, const int32_t *d_count, int lo, int hi,
                   hipStream_t s)
@@ -617,7 +663,7 @@ int kara_launch_t(const Ctx *c, const uint32_t *in, const uint32_t *testv,
     const Shape &sh = c->sh;
     const size_t smem = KSmem<N>::total(sh.R, sh.n);
     const int grid = (B + C::GPW - 1) / C::GPW;
-    hipLaunchKernelGGL((k_bootstrap_int8_kara<N, L, S>), dim3(grid),
+    hipLaunchKernelGGL((k_bootstrap_int8_kara<N, L, S, BB>), dim3(grid),
                        dim3(C::THREADS), smem, s, c->bsk_k8, c->corr_k8, in,
                        testv, out, B, d_count, lo, hi, sh.n, sh.beta, sh.l,
                        sh.S);
@@ -631,18 +677,20 @@ int kara_launch_n(const Ctx *c, const uint32_t *in, const uint32_t *testv,
                   hipStream_t s)
 {
     const Shape &sh = c->sh;
-    if (sh.l == 3 && sh.S == 1)
-        return kara_launch_t<N, 3, 1>(c, in, testv, out, B, d_count, lo, hi, s);
+    if (sh.l == 3 && sh.S == 1 && sh.beta == 7)
+        return kara_launch_t<N, 3, 1, 7>(c, in, testv, out, B, d_count, lo, hi,
+                                         s);
     if (sh.l == 2 && sh.S == 2)
-        return kara_launch_t<N, 2, 2>(c, in, testv, out, B, d_count, lo, hi, s);
-    return kara_launch_t<N, 0, 0>(c, in, testv, out, B, d_count, lo, hi, s);
+        return kara_launch_t<N, 2, 2, 0>(c, in, testv, out, B, d_count, lo, hi,
+                                         s);
+    return kara_launch_t<N, 0, 0, 0>(c, in, testv, out, B, d_count, lo, hi, s);
 }
 
-template <int N, int L, int S>
+template <int N, int L, int S, int BB>
 int kara_attr_t()
 {
     CGGI_HIP_TRY(hipFuncSetAttribute(
-        reinterpret_cast<const void *>(&k_bootstrap_int8_kara<N, L, S>),
+        reinterpret_cast<const void *>(&k_bootstrap_int8_kara<N, L, S, BB>),
         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     return CGGI_OK;
 }
@@ -673,12 +721,12 @@ int kara_make_key_n(Ctx *c, const uint32_t *bsk, hipStream_t s)
                        c->corr_k8, sh.n, sh.l, sh.S);
     CGGI_HIP_TRY(hipGetLastError());
     int rc;
-    if (sh.l == 3 && sh.S == 1)
-        rc = kara_attr_t<N, 3, 1>();
+    if (sh.l == 3 && sh.S == 1 && sh.beta == 7)
+        rc = kara_attr_t<N, 3, 1, 7>();
     else if (sh.l == 2 && sh.S == 2)
-        rc = kara_attr_t<N, 2, 2>();
+        rc = kara_attr_t<N, 2, 2, 0>();
     else
-        rc = kara_attr_t<N, 0, 0>();
+        rc = kara_attr_t<N, 0, 0, 0>();
     return rc;
 }
 
