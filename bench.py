@@ -115,7 +115,9 @@ def int8_kernel_name(p, kind):
     if (L, S) not in ((3, 1), (2, 2)):
         L, S = 0, 0
     if kind == "kara2":
-        return f"k_bootstrap_int8_kara<{p.N}, {L}, {S}>"
+        # the Karatsuba kernel fixes the digit width for l = 3, Bg = 2^7
+        bb = 7 if (L, S) == (3, 1) and p.bg_bit == 7 else 0
+        return f"k_bootstrap_int8_kara<{p.N}, {L}, {S}, {bb}>"
     tiles = {"tiles1": 1, "tiles2": 2, "tiles4": 4}.get(kind, 4)
     return f"k_bootstrap_int8<{p.N}, {L}, {S}, {tiles}>"
 

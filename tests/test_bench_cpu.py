@@ -30,7 +30,9 @@ def test_int8_ops_karatsuba_and_kernel_lookup():
     assert bench.int8_kind_for(plan, 512) == "tiles2"
     assert bench.int8_kind_for(plan, 1024) == "kara2"
     assert bench.int8_kernel_name(params.DEFAULT, "kara2") == \
-        "k_bootstrap_int8_kara<1024, 3, 1>"
+        "k_bootstrap_int8_kara<1024, 3, 1, 7>"
+    assert bench.int8_kernel_name(params.TOY, "kara2") == \
+        "k_bootstrap_int8_kara<256, 2, 2, 0>"
     assert bench.int8_kernel_name(params.DEFAULT, "tiles4") == \
         "k_bootstrap_int8<1024, 3, 1, 4>"
     assert bench.int8_kernel_name(params.LARGE, "tiles4") == \
