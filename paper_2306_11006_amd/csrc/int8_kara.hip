@@ -38,10 +38,10 @@
 // [0, 127]: non-negative operands cost the matrix cores less energy) and
 // the P1 and P2 accumulators of limb 0 start from minus the offsets'
 // contribution, a function of the key only (k_kara_corr); E - O stays
-// signed.  Key
-// windows (one byte-exact copy per stage, double-buffered, prefetched from
-// global memory a stage ahead) are read as five aligned dwords per lane and
-// byte-aligned in registers.
+// signed.  Key windows are wave-private: each wave reads the windows of its
+// own (c', P, limb pair) from global memory a stage ahead and writes them to
+// LDS as four byte-shifted copies, so a lane reads its 16-byte Toeplitz row
+// as four aligned dwords.
 #include "internal.hpp"
 
 #include <type_traits>
@@ -152,8 +152,10 @@ __global__ void k_kara_key(const uint32_t *__restrict__ bsk,
 // W_Delta[rho] = sum_kappa h_ext[32 Delta + rho - kappa] * 2^(7s) the row
 // sum of Toeplitz block Delta of that row's half key h, total = the sum over
 // every Delta, head_J = the sum over Delta <= J (blocks read from the
-// positive copy).  corr [n][2][2][H] (step, c', P, m) holds that excess mod
-// 2^32.  One workgroup per (i, c', P).
+// positive copy).  corr [n][2][2][H] (step, c', P, m) holds minus that
+// excess mod 2^32, the start value of the limb-0 accumulators as is (so the
+// bootstrap kernel uses the loaded words only at its first MFMA and the read
+// latency hides behind the decomposition).  One workgroup per (i, c', P).
 template <int N>
 __global__ __launch_bounds__(256) void k_kara_corr(
     const uint32_t *__restrict__ bsk, uint32_t *__restrict__ corr, int n,
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_kara_corr(
     for (int k = 0; k < PT; ++k) {
         const int j = tid + 256 * k;
         if (j < H)
-            corr[(((size_t)i * 2 + cp) * 2 + P) * H + j] = accv[k];
+            corr[(((size_t)i * 2 + cp) * 2 + P) * H + j] = 0u - accv[k];
     }
 }
 
@@ -355,12 +357,25 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     // the rotations of the next step during the current one.
     constexpr int ROWI = N / 8, GLI = 2 * ROWI, NCH = GPW * GLI / 64;
     constexpr int CPW = (NCH + THREADS / 64 - 1) / (THREADS / 64);
-    int e_cur[CPW], e_nxt[CPW];
-    auto load_e = [&](int ii, int (&dst)[CPW]) {
+    // chunk it of this wave, or -1
+    auto chunk_of = [&](int it) -> int {
+        const int ch = wave + (THREADS / 64) * it;
+        return ch < NCH ? ch : -1;
+    };
+    // The raw input words, modulus-switched where used.  They are read with
+    // vector loads (an opaque zero lane offset keeps the compiler from a
+    // scalar load, whose counter LDS waits share: an outstanding one turns
+    // every LDS wait into a full one) and moved to scalar registers at use.
+    uint32_t e_cur[CPW], e_nxt[CPW];
+    auto load_e = [&](int ii, uint32_t (&dst)[CPW]) {
+        int z = 0;
+        asm volatile("" : "+v"(z));
 #pragma unroll
         for (int it = 0; it < CPW; ++it) {
-            const int ch = wave + (THREADS / 64) * it;
-            dst[it] = ch < NCH ? msw(ch * 64 / GLI, ii) : 0;
+            const int ch = chunk_of(it);
+            const int g = g0 + ch * 64 / GLI;
+            dst[it] = ch >= 0 && g < count
+                          ? in[(size_t)g * (n + 1) + ii + z] : 0u;
         }
     };
     load_e(0, e_cur);
@@ -370,7 +385,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     for (int i = 0; i < n; ++i) {
         kara_barrier();   // ACC of the previous step complete
         // limb-0 accumulators of P1 / P2 start from minus the step's offset
-        // correction (the same for both tiles: it depends on the key only)
+        // correction (the same for both tiles: it depends on the key only;
+        // the table holds it negated)
         kv16i cinit = {};
         if (corr_wave) {
             const uint32_t *cr = corr + (((size_t)i * 2 + cp) * 2 + P) * H +
@@ -380,14 +396,14 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
                 const kv4i c4 = *reinterpret_cast<const kv4i *>(cr + 8 * g);
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    cinit[4 * g + e] = -c4[e];
+                    cinit[4 * g + e] = c4[e];
             }
         }
         // ---- rotate, subtract, decompose into E, O and E - O operands -----
 #pragma unroll
         for (int it = 0; it < CPW; ++it) {
-            const int ch = wave + (THREADS / 64) * it;
-            if (ch >= NCH)
+            const int ch = chunk_of(it);
+            if (ch < 0)
                 break;
             const int gl = ch * 64 / GLI;
             const int rem = ch * 64 - gl * GLI + lane;
@@ -398,7 +414,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             // O[h - f - 1] and E[h - f] (pe = 1) for the even and odd
             // coefficients; a half index u < 0 wraps to u + H with the sign
             // flipped per wrap (Z^H = -1): bit log2(H) of u.
-            const int e = e_cur[it];
+            const int e = (int)kara_modswitch(
+                __builtin_amdgcn_readfirstlane(e_cur[it]), LOG2_2N);
             const int f = e >> 1, pe = e & 1;
             const int h0 = m0 >> 1;
             const uint32_t *Ec = acc + gl * GST + c * 2 * AH;
@@ -407,19 +424,29 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const uint32_t *srcO = pe ? Ec : Oc;
             const int uE = h0 - f - pe, uO = h0 - f;
             const uint32_t *sE = Ec + h0 + (h0 >> 5);   // 4 unrotated entries
-            auto rot = [&](const uint32_t *src, int u) {
-                const int x = u & (H - 1);
-                const uint32_t v = src[x + (x >> 5)];
-                // all ones when bit log2(H) of u is set
-                const uint32_t mk = (uint32_t)__builtin_amdgcn_sbfe(
-                    u, __builtin_ctz(H), 1);
-                return (v ^ mk) - mk;
-            };
-            uint32_t w8[8];
+            // all sixteen reads first (the LDS latency is paid once per
+            // chunk, not once per coefficient), then the arithmetic
+            uint32_t rv[8], sv[8];
+            int uu[8];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                w8[2 * kk] = rot(srcE, uE + kk) - sE[kk] + dig_off;
-                w8[2 * kk + 1] = rot(srcO, uO + kk) - sE[AH + kk] + dig_off;
+                uu[2 * kk] = uE + kk;
+                uu[2 * kk + 1] = uO + kk;
+                const int xe = uu[2 * kk] & (H - 1);
+                const int xo = uu[2 * kk + 1] & (H - 1);
+                rv[2 * kk] = srcE[xe + (xe >> 5)];
+                rv[2 * kk + 1] = srcO[xo + (xo >> 5)];
+                sv[2 * kk] = sE[kk];
+                sv[2 * kk + 1] = sE[AH + kk];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            uint32_t w8[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                // all ones when bit log2(H) of u is set: the wrapped sign
+                const uint32_t mk = (uint32_t)__builtin_amdgcn_sbfe(
+                    uu[k], __builtin_ctz(H), 1);
+                w8[k] = ((rv[k] ^ mk) - mk) - sv[k] + dig_off;
             }
             // half-length coefficients mh0 .. mh0+3; byte b of a dword holds
             // coefficient mh0 + 3 - b (reversed kappa)
@@ -488,16 +515,12 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             }
         }
         kara_barrier();
-        if (i + 1 < n)
-            load_e(i + 1, e_nxt);
 
         // ---- K loop: digit polynomials x block offsets ----------------------
         auto stage = [&](const int kb, auto first_c) {
             constexpr bool FIRST = decltype(first_c)::value;
             const int st = i * R + kb;
             const bool more = st + 1 < n * R;
-            if (more && st >= 1)
-                fetch(st + 1);
             const uint32_t *wb = winw + a_w0;
             // B: this lane's 16 bytes of digit block (J - Delta) mod NBH of
             // tile 0 (tile 1 lies TS bytes further), from the negated copy
@@ -555,6 +578,13 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             load_a(0, af[0]);
             load_b(0, bf[0]);
             group(0, 0, FIRST);   // the first stage starts the accumulators
+            // the next stage's windows, read once this stage's first MFMAs
+            // are issued (before them, the wait of the step's first MFMA
+            // for the correction start values would cover these reads too)
+            if (more && st >= 1)
+                fetch(st + 1);
+            if (FIRST && i + 1 < n)
+                load_e(i + 1, e_nxt);   // next step's rotations
 #pragma unroll 1
             for (int dl = 1; dl + 1 < NBH; dl += 2) {
                 group(dl, 1, false);
