@@ -253,7 +253,6 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     // wave index as a scalar: everything derived from it is wave-uniform
-    // wave index as a scalar: everything derived from it is wave-uniform
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
     // accumulator word of coefficient j (0 <= j < N) of component c
@@ -409,8 +408,8 @@ __global__ __launch_bounds__(KCfg<N>::THREADS, 1) void k_bootstrap_int8_kara(
             const int rem = ch * 64 - gl * GLI + lane;
             const int c = rem / ROWI;
             const int m0 = 8 * (rem - c * ROWI);
-            // In halves (even E, odd O; h = m >> 1) with e = 2 f + pe, the
-            // rotation X^(-e) reads E[h - f] and O[h - f] (pe = 0) or
+            // (X^e ACC)[m] = ACC[m - e].  In halves (even E, odd O; h = m >> 1)
+            // with e = 2 f + pe, that reads E[h - f] and O[h - f] (pe = 0) or
             // O[h - f - 1] and E[h - f] (pe = 1) for the even and odd
             // coefficients; a half index u < 0 wraps to u + H with the sign
             // flipped per wrap (Z^H = -1): bit log2(H) of u.
