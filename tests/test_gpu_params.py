@@ -1,6 +1,7 @@
 """Parameter sets beyond the three named ones: ring degree 512, digit widths
 that take the int8 form's generic (run-time l, S) kernel and its 7-bit
-sub-digit split, and key-switch bases from 2^1 to 2^4 (int8 GEMM key
+sub-digit split, the default 7-bit digits at rings 256 and 512, and
+key-switch bases from 2^1 to 2^4 (int8 GEMM key
 switch) and 2^5 (row-gather key switch).  Both forms (the int8 form under
 its built-in plan and with each throughput kernel forced) and the key
 switch are compared with the oracle coefficient by coefficient on uniform
@@ -35,6 +36,14 @@ SETS = [
     # N=256, Bg=2^5 l=5: ten digit rows per CMux step, generic kernel
     params.Params("n256_bg5_l5", n=48, N=256, k=1, bg_bit=5, l=5,
                   ks_base_bit=2, ks_t=7, lwe_noise_log2=15,
+                  bk_noise_log2=25),
+    # N=512 and N=256 with the default digits (Bg=2^7 l=3): the kernels that
+    # fix the 7-bit digit width at compile time, at the two smaller rings
+    params.Params("n512_bg7_l3", n=56, N=512, k=1, bg_bit=7, l=3,
+                  ks_base_bit=2, ks_t=8, lwe_noise_log2=15,
+                  bk_noise_log2=25),
+    params.Params("n256_bg7_l3", n=40, N=256, k=1, bg_bit=7, l=3,
+                  ks_base_bit=2, ks_t=8, lwe_noise_log2=15,
                   bk_noise_log2=25),
     # key-switch base 2^5: past the int8 GEMM's one-hot width, so the key
     # switch gathers key rows instead
