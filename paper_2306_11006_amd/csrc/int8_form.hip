@@ -232,8 +232,11 @@ struct I8Smem {
 // a~_i = ms[i] (X^(a~_i) ACC - ACC), add the digit offset and split each
 // coefficient into R signed int8 digit operands, in both signs (ArctyrEX
 // Fig. 1, the decomposition of the CMux step; Section 2.2).
-// Layout of dig: [GPW][R][2 signs][N] bytes; within a polynomial the 16
-// bytes of each lane's B operand hold one 32-block's kappa in reverse.
+// Layout of dig: [GPW][R][kappa half][sign: -, +][NB][16] bytes (the 16
+// bytes of a lane's B operand hold one 32-block's kappa half in reverse).
+// Each kappa half holds the negated blocks followed by the blocks, so the
+// sign-rotated block (J - Delta) mod NB the K loops read is block
+// NB + J - Delta of that half: linear in the block offset Delta.
 // NC = 1 decomposes component c_sel only, into rows 0 .. l*SS - 1 (R then
 // counts the rows per bootstrap of that layout).
 // OFF stores each sub-digit delta as delta + 64 and its negation as
@@ -269,7 +272,7 @@ __device__ __forceinline__ void decompose_acc(
         // byte b of the dword holds coefficient m0 + 3 - b (reversed kappa)
         int kap0 = m0 & 31, M = m0 >> 5;
         int kp = 28 - kap0;                 // kappa' of byte 0
-        int off = (kp >> 4) * (NB * 16) + M * 16 + (kp & 15);
+        int off = (kp >> 4) * (2 * NB * 16) + M * 16 + (kp & 15);
         int8_t *gbase = dig + (size_t)gl * R * 2 * N + off;
 #pragma unroll
         for (int p = 1; p <= (L ? L : 8); ++p) {
@@ -309,8 +312,8 @@ __device__ __forceinline__ void decompose_acc(
                 }
                 int kb = ((NC == 2 ? c * l : 0) + (p - 1)) * SS + s;
                 int8_t *base = gbase + (size_t)kb * 2 * N;
-                *reinterpret_cast<uint32_t *>(base) = pos;
-                *reinterpret_cast<uint32_t *>(base + N) = neg;
+                *reinterpret_cast<uint32_t *>(base + NB * 16) = pos;
+                *reinterpret_cast<uint32_t *>(base) = neg;
             }
         }
     }
@@ -520,11 +523,12 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
             const uint32_t *eb = ecop + (EBUF == 2 ? (st & 1) : 0) *
                                             (2 * 4 * 4 * CLEN) +
                                  cp * (4 * 4 * CLEN) + a_lane;
+            // block NB + J of this lane's kappa half (see decompose_acc)
             const int8_t *db[WT];
 #pragma unroll
             for (int t = 0; t < WT; ++t)
                 db[t] = dig + ((size_t)(glt[t] * R + kb) * 2) * N +
-                        hh * (NB * 16);
+                        hh * (2 * NB * 16) + 16 * (NB + Jt[t]);
             // A operand of block offset dl: this wave's limb rows of the
             // Toeplitz window
             auto load_a = [&](int dl, v4i (&af)[LPW]) {
@@ -538,14 +542,11 @@ __global__ __launch_bounds__((I8Cfg<N, T>::THREADS), 1) void k_bootstrap_int8(
                 }
             };
             // B operand of block offset dl: the sign-rotated digit blocks of
-            // both tiles
+            // the tiles, block NB + J - dl of the lane's kappa half
             auto load_b = [&](int dl, v4i (&bf)[WT]) {
 #pragma unroll
-                for (int t = 0; t < WT; ++t) {
-                    const int Mb = (Jt[t] - dl) & (NB - 1);
-                    const int sg = Jt[t] < dl ? N : 0;
-                    bf[t] = *reinterpret_cast<const v4i *>(db[t] + sg + Mb * 16);
-                }
+                for (int t = 0; t < WT; ++t)
+                    bf[t] = *reinterpret_cast<const v4i *>(db[t] - 16 * dl);
             };
             // block offsets per wave: NB over the waves that share a
             // (component, limb set)
@@ -860,7 +861,9 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
     const uint32_t bmask = (1u << beta) - 1u;
     const int32_t bhalf = 1 << (beta - 1);
     unsigned long long *xg = xb + (size_t)grp * 2 * G * WORDS;
-    const int8_t *dbase = dig + (size_t)glc * RM * 2 * N + hh * (NB * 16);
+    // block NB + Jc of this lane's kappa half (see decompose_acc)
+    const int8_t *dbase = dig + (size_t)glc * RM * 2 * N +
+                          hh * (2 * NB * 16) + 16 * (NB + Jc);
     constexpr int PW = WORDS / T;                 // words per thread
 
     for (int i = 0; i < n; ++i) {
@@ -889,10 +892,8 @@ __global__ __launch_bounds__(SPLIT_THREADS, 1) void k_bootstrap_int8_split(
                 af[q][2] = (int)apq[2];
                 af[q][3] = (int)apq[3];
             }
-            const int Mb = (Jc - dl) & (NB - 1);
-            const int sg = Jc < dl ? N : 0;
-            bf = *reinterpret_cast<const v4i *>(dbase + (size_t)kb * 2 * N +
-                                                sg + Mb * 16);
+            bf = *reinterpret_cast<const v4i *>(dbase + (size_t)kb * 2 * N -
+                                                16 * dl);
         };
         const int K = RM * ND;
         v16i Cq[LPM] = {};
