@@ -63,6 +63,7 @@ struct cggi_ctx {
     // key switch as an int8 GEMM (bases up to 2^4)
     int8_t *ksk_i8 = nullptr;     // [NT][N][ksj][4][64][16] limb blocks
     int ks_ksj = 0;               // 32-slot K-steps per j
+    int ks_wg_per_cu = 1;         // resident k_ks_mfma workgroups per CU
     // eval_level workspace
     int32_t ws_gates = 0;
     uint32_t *ws_small = nullptr; // [2G][n+1] bootstrap inputs

@@ -384,12 +384,30 @@ int ks_mfma_dispatch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
     const int ng = (nt_tiles + KSM_WAVES - 1) / KSM_WAVES;
     const int waves = (nt_tiles + ng - 1) / ng;
     const int mg = (B + KSM_ITEMS - 1) / KSM_ITEMS;
-    // enough workgroups to fill the GPU twice, at most KSM_JMAX j each
-    int kc = (2 * 256 + mg * ng - 1) / (mg * ng);
-    kc = std::max(kc, (sh.N + KSM_JMAX - 1) / KSM_JMAX);
-    kc = std::min(kc, std::max(1, sh.N / 16));
-    const int jchunk = (sh.N + kc - 1) / kc;
-    kc = (sh.N + jchunk - 1) / jchunk;
+    // Split j into kc ranges (at most KSM_JMAX j each, at least 16).  The
+    // workgroups run in rounds of (CUs x resident workgroups per CU; one at
+    // 212 VGPRs), and a workgroup costs about its j range plus 10 j (the
+    // load of its a' and its atomic fold: fitted to launches of 4 to 64
+    // ranges of 1024 default ciphertexts on the MI355X), so take the split
+    // with the least rounds x (j range + 10), the fewest ranges among
+    // equals.  Filling the GPU twice over instead (528 workgroups, three
+    // rounds) was 27% slower at 1024 default ciphertexts.
+    const long slots = (long)c->cus * c->ks_wg_per_cu;
+    const int kc_lo = (sh.N + KSM_JMAX - 1) / KSM_JMAX;
+    const int kc_hi = std::max(kc_lo, std::max(1, sh.N / 16));
+    int jchunk = (sh.N + kc_lo - 1) / kc_lo;
+    long best = -1;
+    for (int k = kc_lo; k <= kc_hi; ++k) {
+        const int jc = (sh.N + k - 1) / k;
+        const int kk = (sh.N + jc - 1) / jc;
+        const long rounds = ((long)mg * ng * kk + slots - 1) / slots;
+        const long cost = rounds * (jc + 10);
+        if (best < 0 || cost < best) {
+            best = cost;
+            jchunk = jc;
+        }
+    }
+    const int kc = (sh.N + jchunk - 1) / jchunk;
     const size_t total = (size_t)B * (sh.n + 1);
     const int init_blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
     hipLaunchKernelGGL(k_ks_init<LEVEL>, dim3(init_blocks), dim3(256), 0, s,
@@ -445,6 +463,17 @@ int keyswitch_make_key(Ctx *c, hipStream_t s)
                                        "key failed");
     }
     c->ks_ksj = ksj;
+    // resident workgroups per CU of the GEMM at its launch shape (the
+    // split of j over workgroups is sized from it)
+    {
+        const int ng = (nt_tiles + KSM_WAVES - 1) / KSM_WAVES;
+        const int waves = (nt_tiles + ng - 1) / ng;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(&k_ks_mfma<true>),
+                64 * waves, 0) == hipSuccess && nb > 0)
+            c->ks_wg_per_cu = nb;
+    }
     hipLaunchKernelGGL(k_ksk_to_i8, dim3(4096), dim3(256), 0, s, c->ksk,
                        reinterpret_cast<uint32_t *>(c->ksk_i8), sh.n, sh.N,
                        sh.t, sh.gamma, ksj, nt_tiles);
