@@ -9,9 +9,11 @@
 // result equals the integer product, and its low 32 bits are the product
 // mod 2^32.
 //
-// Layout: one workgroup (256 to 1024 threads by N) owns one bootstrap.
+// Layout: one workgroup (256 or 512 threads by N) owns one bootstrap.
 // LDS holds the accumulator (2 x N u32), the 2l digit transforms (2l x N
-// u64) and the two product transforms (2 x N u64).  The transformed key row of step i
+// u64) and the two product transforms (2 x N u64), which at N = 2048
+// overwrite the first two digit transforms (80 KB at l = 2: two workgroups
+// per CU).  The transformed key row of step i
 // ([2l][2][N] u64) streams from L2 / Infinity Cache; it is shared by every
 // workgroup.
 #include "goldilocks.hpp"
@@ -27,12 +29,15 @@ constexpr int NTT_THREADS = 256;   // table kernels
 
 // Threads of a bootstrap workgroup.  The butterflies are VALU-bound with an
 // LDS round trip every three stages, so more waves per SIMD hide more of
-// the LDS latency and barrier skew.  At N = 2048 the workgroup's LDS
-// (113 KB at l = 2) leaves room for one per CU: 16 waves (four per SIMD,
-// within the 96-VGPR budget) run 1.45x faster than 4.  At N = 1024 two
-// workgroups share a CU: 8 waves each (four per SIMD) run 1.1x faster than
-// 4.  Every loop below strides by the thread count, so any count is exact.
-constexpr int bs_threads(int N) { return N >= 2048 ? 1024 : (N >= 1024 ? 512 : 256); }
+// the LDS latency and barrier skew: four per SIMD, from two workgroups of 8
+// waves per CU at N = 1024 (1.1x faster than 4 waves each) and at N = 2048
+// (its 80 KB of LDS leaves room for two; with the product transforms in
+// their own LDS, 113 KB, one workgroup of 16 waves per CU took 76.4 ms per
+// 1024 large bootstraps).  Every loop below strides by the thread count, so
+// any count is exact.
+constexpr int bs_threads(int N) { return N >= 1024 ? 512 : 256; }
+// whether the product transforms overwrite the first two digit transforms
+constexpr bool ntt_products_alias(int N) { return N >= 2048; }
 constexpr uint64_t G_PAPER = 12037493425763644479ull; // order 2^32 mod Q
 
 unsigned bitrev(unsigned x, int bits)
@@ -228,8 +233,10 @@ __device__ __forceinline__ uint32_t modswitch(uint32_t u, int log2_2n)
 }
 
 // One bootstrap per workgroup.
+// at most 128 VGPRs: four waves per SIMD
 template <int N, int TH = bs_threads(N)>
-__global__ __launch_bounds__(TH) void k_bootstrap_ntt(
+__global__ __launch_bounds__(TH) __attribute__((amdgpu_waves_per_eu(4)))
+void k_bootstrap_ntt(
     const uint64_t *__restrict__ bsk_ntt, const uint64_t *__restrict__ tw,
     const uint64_t *__restrict__ twi,
     const uint32_t *__restrict__ in, const uint32_t *__restrict__ testv,
@@ -239,9 +246,15 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
     extern __shared__ __align__(16) unsigned char smem[];
     const int L2 = 2 * l;
     uint64_t *dig = reinterpret_cast<uint64_t *>(smem);          // [2l][N]
-    uint64_t *res = dig + (size_t)L2 * N;                         // [2][N]
-    uint32_t *acc = reinterpret_cast<uint32_t *>(res + 2 * N);    // [2][N]
-    uint16_t *ms = reinterpret_cast<uint16_t *>(acc + 2 * N);     // [n+1]
+    // product transforms [2][N]: at N = 2048 they overwrite digit
+    // transforms 0 and 1 (the pointwise pass reads positions 2j, 2j + 1 of
+    // every digit row before it writes the same two positions of the
+    // products, in the same thread, and no other thread touches them), so
+    // that two workgroups fit a CU; below, they have their own LDS (the
+    // overlap measured 0.2% slower at N = 1024, where it gains no workgroup)
+    uint64_t *res = ntt_products_alias(N) ? dig : dig + (size_t)L2 * N;
+    uint32_t *acc = reinterpret_cast<uint32_t *>(
+        dig + (size_t)(L2 + (ntt_products_alias(N) ? 0 : 2)) * N); // [2][N]
 
     int count = B;
     if (d_count)
@@ -250,14 +263,12 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
     if (g >= count)
         return;
     constexpr int LOG2_2N = __builtin_ctz(2 * N);
+    // the input ciphertext
     const uint32_t *ct = in + (size_t)g * (n + 1);
-    for (int i = threadIdx.x; i <= n; i += TH)
-        ms[i] = (uint16_t)modswitch(ct[i], LOG2_2N);
-    __syncthreads();
 
     // ACC = (0, X^(2N - b~) * v)
     {
-        int e = (2 * N - ms[n]) & (2 * N - 1);
+        int e = (2 * N - (int)modswitch(ct[n], LOG2_2N)) & (2 * N - 1);
         for (int m = threadIdx.x; m < N; m += TH) {
             uint32_t v = testv ? testv[m] : (1u << 29);
             int t = m + e;
@@ -284,8 +295,16 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
     const bool w4_neg = tw[1] != (uint64_t(1) << 48);
     const bool small_digits = beta <= 14;
 
+    // each step's rotation is read a step ahead with a vector load (an
+    // opaque zero offset keeps it off the scalar unit, whose outstanding
+    // loads every LDS wait would also wait for) and made uniform at use
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    uint32_t e_nxt = ct[z];
     for (int i = 0; i < n; ++i) {
-        const int e = ms[i];
+        const int e = (int)modswitch(__builtin_amdgcn_readfirstlane(e_nxt),
+                                     LOG2_2N);
+        e_nxt = ct[i + 1 + z];     // i + 1 <= n: in the ciphertext
         if (e == 0)      // X^0 * ACC - ACC = 0 decomposes to all-zero digits
             continue;
         // (1) rotate, subtract, decompose, and forward stages 0..2: a thread
@@ -397,8 +416,9 @@ __global__ __launch_bounds__(TH) void k_bootstrap_ntt(
 template <int N>
 size_t ntt_smem(int n, int l)
 {
-    return (size_t)2 * l * N * 8 + 2 * N * 8 + 2 * N * 4 +
-           (size_t)(n + 1) * 2 + 16;
+    (void)n;
+    return (size_t)(2 * l + (ntt_products_alias(N) ? 0 : 2)) * N * 8 +
+           2 * N * 4;
 }
 
 } // namespace
@@ -501,8 +521,9 @@ int ntt_bootstrap(const Ctx *c, const uint32_t *in, const uint32_t *testv,
 
 size_t ntt_smem_bytes(int N, int n, int l)
 {
-    return (size_t)2 * l * N * 8 + 2 * N * 8 + 2 * N * 4 +
-           (size_t)(n + 1) * 2 + 16;
+    (void)n;
+    return (size_t)(2 * l + (ntt_products_alias(N) ? 0 : 2)) * N * 8 +
+           2 * N * 4;
 }
 
 } // namespace cggi
