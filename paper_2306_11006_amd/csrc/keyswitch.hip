@@ -391,7 +391,7 @@ int ks_mfma_dispatch(const Ctx *c, const uint32_t *in, uint32_t *out, int B,
     // ranges of 1024 default ciphertexts on the MI355X), so take the split
     // with the least rounds x (j range + 10), the fewest ranges among
     // equals.  Filling the GPU twice over instead (528 workgroups, three
-    // rounds) was 27% slower at 1024 default ciphertexts.
+    // rounds) was 25% slower at 1024 default ciphertexts.
     const long slots = (long)c->cus * c->ks_wg_per_cu;
     const int kc_lo = (sh.N + KSM_JMAX - 1) / KSM_JMAX;
     const int kc_hi = std::max(kc_lo, std::max(1, sh.N / 16));
@@ -471,8 +471,12 @@ int keyswitch_make_key(Ctx *c, hipStream_t s)
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &nb, reinterpret_cast<const void *>(&k_ks_mfma<true>),
-                64 * waves, 0) == hipSuccess && nb > 0)
-            c->ks_wg_per_cu = nb;
+                64 * waves, 0) == hipSuccess) {
+            if (nb > 0)
+                c->ks_wg_per_cu = nb;
+        } else {
+            (void)hipGetLastError();   // keep one per CU; clear the error
+        }
     }
     hipLaunchKernelGGL(k_ksk_to_i8, dim3(4096), dim3(256), 0, s, c->ksk,
                        reinterpret_cast<uint32_t *>(c->ksk_i8), sh.n, sh.N,
